@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Benchmark of the PLAS sort on one MI355X.
+
+Workload: one plain float32 sort of a 1024 x 1024 grid (N = 1,048,576) of
+D = 59 synthetic 3DGS-shaped attribute vectors, channel-major (~247 MB),
+data seed 2, sort seed 0x5EED. A step is one whole sort (ingest, every
+reorder of every radius level, output) with the features already resident
+in device memory. Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD's published peak
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_roofline(res, n: int, d: int) -> dict:
+    """Achieved algorithmic bandwidth of the blur pass and of the assignment
+    kernel, from HIP-event times of the launches of the profiled sorts."""
+    f32 = 4
+    blur_bytes = n * 2 * d * f32                      # read + write one grid per pass
+    moved = sum(t["moved"] for t in res.trace) / max(res.reorders, 1)
+    assign_bytes = n * 2 * d * f32 + moved * (d * f32 + 2 * 4)  # read grid+target; write moved cells + perm
+    out = {}
+    if res.blur_launches:
+        avg = res.blur_ms / res.blur_launches
+        out["blur_pass"] = dict(avg_ms=avg, bytes=blur_bytes, gbs=blur_bytes / (avg * 1e-3) / 1e9)
+    if res.assign_launches:
+        avg = res.assign_ms / res.assign_launches
+        out["assign"] = dict(avg_ms=avg, bytes=assign_bytes, gbs=assign_bytes / (avg * 1e-3) / 1e9,
+                             moved_per_reorder=moved)
+    return out
+
+
+def cpu_baseline(F, side: int, seed: int, reorders_full: int, sample_reorders: int) -> dict:
+    import oracle
+    threads = oracle.set_threads(0)
+    t0 = time.perf_counter()
+    res = oracle.sort(F, side, seed, max_reorders=sample_reorders)
+    dt = time.perf_counter() - t0
+    if res.status != 0:
+        raise RuntimeError(f"oracle failed: {res.status}")
+    per_reorder = dt / max(res.reorders, 1)
+    est = per_reorder * reorders_full
+    n = side * side
+    return {
+        "value": n / est,
+        "unit": "Gaussians/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"CPU oracle on the same {side}x{side} D={F.shape[0]} input, stopped after "
+                   f"{res.reorders} reorders in {dt:.1f} s; value = N / ({per_reorder:.3f} s per reorder "
+                   f"x {reorders_full} reorders of the full sort)"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--side", type=int, default=1024)
+    ap.add_argument("--cpu-sample-reorders", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the PLAS sort of one grid is a single-device "
+              f"workload here (asked for --gpus {args.gpus})", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2312_13299_amd as plas
+    import synthetic
+
+    side = args.side
+    n = side * side
+    seed = synthetic.SORT_SEED
+    F = synthetic.gaussian_attributes(n, synthetic.DATA_SEED_SCENE)
+    d = F.shape[0]
+    f_dev = torch.from_numpy(F).cuda()
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    ctx = plas.Context(0)
+    torch.cuda.synchronize()
+
+    for i in range(args.warmup):
+        _, res = ctx.sort(f_dev, side, seed, out=perm)
+        log(f"warmup {i}: {res.reorders} reorders, {res.levels} levels, {res.total_ms:.1f} ms")
+    torch.cuda.synchronize()
+
+    # Timed region: K whole sorts. The library times its blur and assignment
+    # launches with HIP events on its stream (profile=True).
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, res = ctx.sort(f_dev, side, seed, out=perm, profile=True)
+        results.append(res)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for i, res in enumerate(results):
+        log(f"step {i}: {res.reorders} reorders, {res.total_ms:.1f} ms, blur {res.blur_ms:.1f} ms, "
+            f"assign {res.assign_ms:.1f} ms")
+    res = results[-1]
+    # Sum the event times over all timed steps.
+    agg = plas.SortResult(reorders=sum(r.reorders for r in results), levels=res.levels,
+                          energy_fixed=res.energy_fixed, scale_shift=res.scale_shift,
+                          energy=res.energy, trace=[t for r in results for t in r.trace],
+                          blur_ms=sum(r.blur_ms for r in results),
+                          blur_launches=sum(r.blur_launches for r in results),
+                          assign_ms=sum(r.assign_ms for r in results),
+                          assign_launches=sum(r.assign_launches for r in results))
+    kern = kernel_roofline(agg, n, d)
+    dominant = max(kern, key=lambda k: kern[k]["avg_ms"] * (2 if k == "blur_pass" else 1))
+    roof = {
+        "bound": "hbm",
+        "kernel": dominant,
+        "achieved": round(kern[dominant]["gbs"], 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(kern[dominant]["gbs"] / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "per_launch_bytes": int(kern[dominant]["bytes"]),
+        "avg_launch_ms": round(kern[dominant]["avg_ms"], 5),
+        "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kern.items()},
+    }
+    ms_per_step = elapsed / args.steps * 1e3
+    value = n * args.steps / elapsed
+    line = {
+        "metric": "Gaussians sorted/s at 1024^2 D=59",
+        "value": round(value, 1),
+        "unit": "Gaussians/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"plas_sort_{side}x{side}_d{d}_f32",
+            "side": side, "n": n, "d": d, "layout": "channel-major",
+            "data_seed": synthetic.DATA_SEED_SCENE, "sort_seed": seed,
+            "reorders": res.reorders, "levels": res.levels,
+            "energy_mean": res.energy,
+        },
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(F, side, seed, res.reorders, args.cpu_sample_reorders)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,159 @@
+/*
+ * plas.h -- C ABI of the MI355X (gfx950) PLAS library, libplas.so.
+ *
+ * PLAS (Parallel Linear Assignment Sorting) arranges N feature vectors on a
+ * side x side grid (N = side^2) so that neighbouring cells hold similar
+ * vectors. It is the sort of Sec. 3.1 ("Sorting High Dimensional Gaussians
+ * into 2D Grids") of "Compact 3D Scene Representation via Self-Organizing
+ * Gaussian Grids" (arXiv 2312.13299): starting from a random arrangement it
+ * repeatedly blurs the grid into a target and reassigns random groups of four
+ * cells by the best of their 24 permutations, with a shrinking blur radius.
+ *
+ * Every step runs in HIP kernels on the device; the host only validates
+ * arguments, sequences launches and copies small results back.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named as device pointers must point to device memory of the
+ *    handle's device (e.g. a torch CUDA tensor's data_ptr()); the library
+ *    never frees them. Host pointers (stats, trace, scalar outputs) are
+ *    caller-owned host memory.
+ *  - Cells are row-major: cell p = y * side + x.
+ *  - A permutation is in gather form: perm[p] is the index of the vector
+ *    that sits at cell p (arranged = features[perm]).
+ *  - Functions return PLAS_OK (0) or a negative status; they never throw
+ *    across the ABI. plas_last_error() gives a message for the last failure
+ *    on a handle.
+ *  - Work is ordered on the handle's stream (plas_set_stream). Calls that
+ *    fill host outputs synchronise that stream before returning.
+ *  - One handle per host thread; a handle is not thread-safe.
+ */
+#ifndef PLAS_H
+#define PLAS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PLAS_ABI_VERSION 1
+
+/* Status codes. */
+#define PLAS_OK 0
+#define PLAS_ERR_INVALID_ARGUMENT (-1) /* NULL pointer, n != side^2, side < 2, bad d/layout/radius, init_perm not a bijection */
+#define PLAS_ERR_UNSUPPORTED (-2)      /* a dtype or channel count this build does not handle */
+#define PLAS_ERR_OUT_OF_MEMORY (-3)    /* the device workspace could not be allocated */
+#define PLAS_ERR_HIP (-4)              /* a HIP runtime call failed; see plas_last_error */
+#define PLAS_ERR_NONFINITE (-5)        /* a feature value is NaN or infinite */
+
+/* Feature layouts. */
+#define PLAS_LAYOUT_CN 0 /* channel-major: features[c * n + i] */
+#define PLAS_LAYOUT_NC 1 /* vector-major:  features[i * d + c] */
+
+/* Feature element types. */
+#define PLAS_DTYPE_F32 0
+#define PLAS_DTYPE_BF16 1 /* not built yet: PLAS_ERR_UNSUPPORTED */
+
+/* Largest channel count d of the float32 path. */
+#define PLAS_MAX_CHANNELS 64
+
+typedef struct plas_context* plas_handle;
+
+/*
+ * Sort parameters. Defaults (plas_sort_params_init) follow Sec. 3.1:
+ * radius decay 0.95, a 0.01 % improvement threshold, blocks of at least 16,
+ * start radius side/2 - 1.
+ */
+typedef struct {
+    uint32_t struct_size;    /* sizeof(plas_sort_params); set by plas_sort_params_init */
+    uint32_t inv_threshold;  /* M: a reorder improves if E_prev - E >= ceil(E_prev / M); 10000 */
+    uint64_t seed;           /* names every random draw (start, grouping, shifts) */
+    double radius_decay;     /* phi <- decay * phi at each level; 0.95; must be in (0, 1) */
+    double start_radius;     /* <= 0: side/2 - 1; raised to 1 if below */
+    int64_t max_reorders;    /* 0: run the whole schedule; > 0: stop after this many reorders */
+    const int32_t* init_perm;/* device int32[n] start arrangement (gather form), or NULL for the seeded random start */
+    int32_t min_block;       /* smallest block side; 16 */
+    int32_t profile;         /* nonzero: time the blur and assignment kernels with HIP events (fills *_ms in stats) */
+    int32_t reorders_per_sync; /* reorders queued between checks of the device's done flag; 0: library default */
+    int32_t reserved;
+} plas_sort_params;
+
+/* One radius level of a finished sort. */
+typedef struct {
+    double phi;            /* real radius */
+    int32_t r;             /* blur half-width floor(phi) */
+    int32_t beta;          /* block side */
+    int64_t reorders;      /* reorders run at this level */
+    uint64_t energy_fixed; /* integer energy after the level's last reorder */
+    uint64_t moved;        /* cells that changed place over the level */
+} plas_level_stat;
+
+typedef struct {
+    uint32_t struct_size;   /* sizeof(plas_sort_stats); the caller sets it */
+    int32_t levels;         /* levels that ran at least one reorder */
+    int64_t reorders;       /* blockwise assignments run in total */
+    uint64_t energy_fixed;  /* integer energy after the last reorder */
+    int32_t scale_shift;    /* s: energies are sums of floor(d * 2^s) */
+    int32_t trace_len;      /* entries written to trace */
+    double energy;          /* energy_fixed * 2^-s / n: mean squared distance to the target */
+    plas_level_stat* trace; /* caller-owned host array, may be NULL */
+    int32_t trace_cap;      /* its capacity */
+    int32_t reserved;
+    /* With params->profile: summed device time and launch counts. */
+    double blur_ms;         /* both blur passes */
+    int64_t blur_launches;  /* passes (two per reorder) */
+    double assign_ms;       /* assignment kernel */
+    int64_t assign_launches;
+    double total_ms;        /* wall time of the whole call */
+} plas_sort_stats;
+
+int32_t plas_get_abi_version(void);
+
+/* Fill p with the defaults above. Returns PLAS_ERR_INVALID_ARGUMENT for NULL. */
+int32_t plas_sort_params_init(plas_sort_params* p);
+
+/* Create a context on HIP device `device`. The device workspace is allocated
+ * on first use and kept, grown as needed, until plas_destroy. */
+int32_t plas_create(plas_handle* out, int32_t device);
+
+/* Release the context and its workspace. NULL is allowed. */
+int32_t plas_destroy(plas_handle h);
+
+/* Order all further work on `stream` (a hipStream_t; NULL = the null
+ * stream). Python passes torch.cuda.current_stream().cuda_stream. */
+int32_t plas_set_stream(plas_handle h, void* stream);
+
+/*
+ * Sort (Sec. 3.1). features: device array of n = side^2 vectors of d
+ * channels (1 <= d <= PLAS_MAX_CHANNELS) in `layout`, element type `dtype`;
+ * read only. perm_out: device int32[n], written in gather form. stats: host
+ * memory or NULL. The call returns when the sort has finished on the device.
+ * Deterministic: the same inputs and seed give the same permutation, equal
+ * bit for bit to the CPU oracle's.
+ */
+int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int32_t side,
+                  int32_t layout, int32_t dtype, const plas_sort_params* params,
+                  int32_t* perm_out, plas_sort_stats* stats);
+
+/*
+ * Energy of an arrangement (the distance of Sec. 3.1 that the sort
+ * minimises): arranged = features[perm] (perm: device int32[n] in gather
+ * form, or NULL for the identity), target = box blur of half-width `radius`
+ * (>= 0), energy = sum over cells of floor(d(arranged[p], target[p]) * 2^s),
+ * with s derived from the features' per-channel ranges. Host outputs may be
+ * NULL. energy_mean = energy * 2^-s / n.
+ */
+int32_t plas_grid_energy(plas_handle h, const void* features, const int32_t* perm, int64_t n,
+                         int32_t d, int32_t side, int32_t layout, int32_t dtype, int32_t radius,
+                         uint64_t* energy_fixed, int32_t* scale_shift, double* energy_mean);
+
+/* A static string naming a status code. */
+const char* plas_status_string(int32_t status);
+
+/* The message of the last failure on h (empty if none). Valid until the next call on h. */
+const char* plas_last_error(plas_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

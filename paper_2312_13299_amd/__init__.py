@@ -1,0 +1,419 @@
+"""Python binding of libplas.so, the MI355X (gfx950) implementation of
+Parallel Linear Assignment Sorting (PLAS), the sort of Sec. 3.1 of
+"Compact 3D Scene Representation via Self-Organizing Gaussian Grids"
+(arXiv 2312.13299).
+
+This module only marshals arguments: torch tensors are passed to the C ABI
+(include/plas.h) as device pointers and the current HIP stream, and every
+step of the sort runs in the library's HIP kernels. There is no fallback: if
+libplas.so is missing or cannot be loaded, every entry point raises.
+
+    perm, stats = paper_2312_13299_amd.sort(features_cn, side=1024, seed=0x5EED)
+    arranged = features_cn[:, perm]          # channel-major grid, row-major cells
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBRARY = os.path.join(HERE, "libplas.so")
+
+OK = 0
+ERR_INVALID_ARGUMENT = -1
+ERR_UNSUPPORTED = -2
+ERR_OUT_OF_MEMORY = -3
+ERR_HIP = -4
+ERR_NONFINITE = -5
+
+LAYOUT_CN = 0
+LAYOUT_NC = 1
+DTYPE_F32 = 0
+DTYPE_BF16 = 1
+MAX_CHANNELS = 64
+
+# Every symbol declared in include/plas.h and include/plas_stages.h.
+EXPORTS = (
+    "plas_get_abi_version", "plas_sort_params_init", "plas_create", "plas_destroy",
+    "plas_set_stream", "plas_sort", "plas_grid_energy", "plas_status_string", "plas_last_error",
+    "plas_stage_blur", "plas_stage_group_table", "plas_stage_assign", "plas_stage_energy",
+    "plas_stage_bijection", "plas_philox4x64_10", "plas_draw", "plas_schedule",
+    "plas_scale_shift_from_ranges",
+)
+
+
+class PlasError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"PLAS status {status}: {message}")
+        self.status = status
+
+
+class SortParams(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("inv_threshold", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
+        ("radius_decay", ctypes.c_double),
+        ("start_radius", ctypes.c_double),
+        ("max_reorders", ctypes.c_int64),
+        ("init_perm", ctypes.c_void_p),
+        ("min_block", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
+        ("reorders_per_sync", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class LevelStat(ctypes.Structure):
+    _fields_ = [
+        ("phi", ctypes.c_double),
+        ("r", ctypes.c_int32),
+        ("beta", ctypes.c_int32),
+        ("reorders", ctypes.c_int64),
+        ("energy_fixed", ctypes.c_uint64),
+        ("moved", ctypes.c_uint64),
+    ]
+
+
+class SortStats(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("levels", ctypes.c_int32),
+        ("reorders", ctypes.c_int64),
+        ("energy_fixed", ctypes.c_uint64),
+        ("scale_shift", ctypes.c_int32),
+        ("trace_len", ctypes.c_int32),
+        ("energy", ctypes.c_double),
+        ("trace", ctypes.POINTER(LevelStat)),
+        ("trace_cap", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("blur_ms", ctypes.c_double),
+        ("blur_launches", ctypes.c_int64),
+        ("assign_ms", ctypes.c_double),
+        ("assign_launches", ctypes.c_int64),
+        ("total_ms", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """Load libplas.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBRARY):
+        raise ImportError(f"{LIBRARY} is missing: build it with paper_2312_13299_amd/build.py "
+                          "(or __graft_entry__.build()); there is no fallback path")
+    L = ctypes.CDLL(LIBRARY)
+    vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    sigs = {
+        "plas_get_abi_version": (i32, []),
+        "plas_sort_params_init": (i32, [ctypes.POINTER(SortParams)]),
+        "plas_create": (i32, [ctypes.POINTER(vp), i32]),
+        "plas_destroy": (i32, [vp]),
+        "plas_set_stream": (i32, [vp, vp]),
+        "plas_sort": (i32, [vp, vp, i64, i32, i32, i32, i32, ctypes.POINTER(SortParams), vp,
+                            ctypes.POINTER(SortStats)]),
+        "plas_grid_energy": (i32, [vp, vp, vp, i64, i32, i32, i32, i32, i32, u64p, i32p,
+                                   ctypes.POINTER(ctypes.c_double)]),
+        "plas_status_string": (ctypes.c_char_p, [i32]),
+        "plas_last_error": (ctypes.c_char_p, [vp]),
+        "plas_stage_blur": (i32, [vp, vp, vp, i32, i32, i32]),
+        "plas_stage_group_table": (i32, [vp, i32, u64p, vp]),
+        "plas_stage_assign": (i32, [vp, vp, vp, vp, i32, i32, i32, i32, i32, u64p, i32, u64p, u64p]),
+        "plas_stage_energy": (i32, [vp, vp, vp, i32, i32, i32, u64p]),
+        "plas_stage_bijection": (i32, [vp, i64, u64p, vp]),
+        "plas_philox4x64_10": (None, [u64p, u64p, u64p]),
+        "plas_draw": (None, [u64, u64, u64, u64p]),
+        "plas_schedule": (i32, [i32, ctypes.c_double, i32, ctypes.c_double, vp, vp, vp, i32]),
+        "plas_scale_shift_from_ranges": (i32, [vp, vp, i32, i64, i32p]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    if L.plas_get_abi_version() != 1:
+        raise ImportError("libplas.so ABI version mismatch")
+    _lib = L
+    return L
+
+
+def _u64x4(values):
+    arr = (ctypes.c_uint64 * 4)()
+    for i, v in enumerate(values):
+        arr[i] = int(v) & 0xFFFFFFFFFFFFFFFF
+    return arr
+
+
+# --------------------------------------------------------- host-side helpers
+
+def philox4x64_10(ctr, key) -> list[int]:
+    out = (ctypes.c_uint64 * 4)()
+    k = (ctypes.c_uint64 * 2)(*(int(v) & 0xFFFFFFFFFFFFFFFF for v in key))
+    library().plas_philox4x64_10(_u64x4(ctr), k, out)
+    return [int(v) for v in out]
+
+
+def draw(seed: int, purpose: int, index: int) -> list[int]:
+    out = (ctypes.c_uint64 * 4)()
+    library().plas_draw(seed & 0xFFFFFFFFFFFFFFFF, purpose, index, out)
+    return [int(v) for v in out]
+
+
+def schedule(side: int, decay: float = 0.95, min_block: int = 16, start_radius: float = 0.0):
+    L = library()
+    count = L.plas_schedule(side, decay, min_block, start_radius, None, None, None, 0)
+    if count < 0:
+        raise PlasError(count, "bad schedule arguments")
+    phi = (ctypes.c_double * count)()
+    r = (ctypes.c_int32 * count)()
+    beta = (ctypes.c_int32 * count)()
+    L.plas_schedule(side, decay, min_block, start_radius, phi, r, beta, count)
+    return list(phi), list(r), list(beta)
+
+
+def scale_shift_from_ranges(mins, maxs, n: int) -> int:
+    d = len(mins)
+    lo = (ctypes.c_float * d)(*mins)
+    hi = (ctypes.c_float * d)(*maxs)
+    s = ctypes.c_int32()
+    st = library().plas_scale_shift_from_ranges(lo, hi, d, n, ctypes.byref(s))
+    if st != OK:
+        raise PlasError(st, "bad ranges")
+    return s.value
+
+
+def status_string(status: int) -> str:
+    return library().plas_status_string(status).decode()
+
+
+# ------------------------------------------------------------------ context
+
+def padded_channels(d: int) -> int:
+    dp = 4
+    while dp < d:
+        dp *= 2
+    return dp
+
+
+class Context:
+    """A library context on one device. Work goes to torch's current stream
+    of that device at each call."""
+
+    def __init__(self, device: int = 0):
+        self._h = ctypes.c_void_p()
+        self.device = device
+        st = library().plas_create(ctypes.byref(self._h), device)
+        if st != OK:
+            raise PlasError(st, f"plas_create failed on device {device}: {status_string(st)}")
+
+    def close(self):
+        if self._h:
+            library().plas_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, what: str):
+        if st != OK:
+            msg = library().plas_last_error(self._h).decode() or status_string(st)
+            raise PlasError(st, f"{what}: {msg}")
+
+    def _bind_stream(self):
+        import torch
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        library().plas_set_stream(self._h, ctypes.c_void_p(stream))
+
+    # ---- whole sort
+
+    def sort(self, features, side: int | None = None, seed: int = 0x5EED, layout: str = "cn", *,
+             radius_decay: float = 0.95, inv_threshold: int = 10000, min_block: int = 16,
+             start_radius: float = 0.0, max_reorders: int = 0, init_perm=None,
+             profile: bool = False, reorders_per_sync: int = 0, out=None):
+        """Sort device features ([d][n] for layout "cn", [n][d] for "nc",
+        float32, contiguous) onto a side x side grid. Returns (perm, stats):
+        perm is an int32 device tensor in gather form, stats a SortResult."""
+        import torch
+        _check_tensor(features, torch.float32)
+        if layout == "cn":
+            d, n = features.shape
+            lay = LAYOUT_CN
+        elif layout == "nc":
+            n, d = features.shape
+            lay = LAYOUT_NC
+        else:
+            raise ValueError(f"unknown layout {layout!r}")
+        if side is None:
+            side = int(round(n ** 0.5))
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device=features.device)
+        _check_tensor(out, torch.int32)
+        prm = SortParams()
+        library().plas_sort_params_init(ctypes.byref(prm))
+        prm.seed = seed & 0xFFFFFFFFFFFFFFFF
+        prm.radius_decay = radius_decay
+        prm.inv_threshold = inv_threshold
+        prm.min_block = min_block
+        prm.start_radius = start_radius
+        prm.max_reorders = max_reorders
+        prm.profile = 1 if profile else 0
+        prm.reorders_per_sync = reorders_per_sync
+        if init_perm is not None:
+            _check_tensor(init_perm, torch.int32)
+            prm.init_perm = init_perm.data_ptr()
+        cap = 4096
+        trace = (LevelStat * cap)()
+        stats = SortStats()
+        stats.struct_size = ctypes.sizeof(SortStats)
+        stats.trace = ctypes.cast(trace, ctypes.POINTER(LevelStat))
+        stats.trace_cap = cap
+        self._bind_stream()
+        st = library().plas_sort(self._h, ctypes.c_void_p(features.data_ptr()), n, d, side, lay,
+                                 DTYPE_F32, ctypes.byref(prm), ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.byref(stats))
+        self._check(st, "plas_sort")
+        res = SortResult(
+            reorders=stats.reorders, levels=stats.levels, energy_fixed=int(stats.energy_fixed),
+            scale_shift=stats.scale_shift, energy=stats.energy,
+            trace=[dict(phi=t.phi, r=t.r, beta=t.beta, reorders=t.reorders,
+                        energy=int(t.energy_fixed), moved=int(t.moved))
+                   for t in trace[: stats.trace_len]],
+            blur_ms=stats.blur_ms, blur_launches=stats.blur_launches,
+            assign_ms=stats.assign_ms, assign_launches=stats.assign_launches,
+            total_ms=stats.total_ms)
+        return out, res
+
+    def grid_energy(self, features, perm=None, side: int | None = None, radius: int = 1,
+                    layout: str = "cn"):
+        """(energy_fixed, scale_shift, energy_mean) of features[perm] at radius."""
+        import torch
+        _check_tensor(features, torch.float32)
+        if layout == "cn":
+            d, n = features.shape
+            lay = LAYOUT_CN
+        else:
+            n, d = features.shape
+            lay = LAYOUT_NC
+        if side is None:
+            side = int(round(n ** 0.5))
+        p = None
+        if perm is not None:
+            _check_tensor(perm, torch.int32)
+            p = ctypes.c_void_p(perm.data_ptr())
+        E, s, mean = ctypes.c_uint64(), ctypes.c_int32(), ctypes.c_double()
+        self._bind_stream()
+        st = library().plas_grid_energy(self._h, ctypes.c_void_p(features.data_ptr()), p, n, d, side,
+                                        lay, DTYPE_F32, radius, ctypes.byref(E), ctypes.byref(s),
+                                        ctypes.byref(mean))
+        self._check(st, "plas_grid_energy")
+        return int(E.value), s.value, mean.value
+
+    # ---- stages (working layout [n][dp] float32)
+
+    def stage_blur(self, grid, side: int, radius: int, target=None):
+        import torch
+        _check_tensor(grid, torch.float32)
+        dp = grid.shape[1]
+        if target is None:
+            target = torch.empty_like(grid)
+        self._bind_stream()
+        self._check(library().plas_stage_blur(self._h, ctypes.c_void_p(grid.data_ptr()),
+                                              ctypes.c_void_p(target.data_ptr()), side, dp, radius),
+                    "plas_stage_blur")
+        return target
+
+    def stage_group_table(self, beta: int, round_keys):
+        import torch
+        table = torch.empty(beta * beta, dtype=torch.int32, device=f"cuda:{self.device}")
+        self._bind_stream()
+        self._check(library().plas_stage_group_table(self._h, beta, _u64x4(round_keys),
+                                                     ctypes.c_void_p(table.data_ptr())),
+                    "plas_stage_group_table")
+        return table
+
+    def stage_assign(self, grid, target, perm, side: int, beta: int, dy: int, dx: int, round_keys,
+                     scale_shift: int):
+        """One reorder in place on grid ([n][dp]) and perm. Returns (energy, moved)."""
+        import torch
+        _check_tensor(grid, torch.float32)
+        _check_tensor(target, torch.float32)
+        _check_tensor(perm, torch.int32)
+        E, M = ctypes.c_uint64(), ctypes.c_uint64()
+        self._bind_stream()
+        self._check(library().plas_stage_assign(
+            self._h, ctypes.c_void_p(grid.data_ptr()), ctypes.c_void_p(target.data_ptr()),
+            ctypes.c_void_p(perm.data_ptr()), side, grid.shape[1], beta, dy, dx, _u64x4(round_keys),
+            scale_shift, ctypes.byref(E), ctypes.byref(M)), "plas_stage_assign")
+        return int(E.value), int(M.value)
+
+    def stage_energy(self, grid, target, side: int, scale_shift: int) -> int:
+        import torch
+        _check_tensor(grid, torch.float32)
+        _check_tensor(target, torch.float32)
+        E = ctypes.c_uint64()
+        self._bind_stream()
+        self._check(library().plas_stage_energy(self._h, ctypes.c_void_p(grid.data_ptr()),
+                                                ctypes.c_void_p(target.data_ptr()), side,
+                                                grid.shape[1], scale_shift, ctypes.byref(E)),
+                    "plas_stage_energy")
+        return int(E.value)
+
+    def stage_bijection(self, n: int, round_keys):
+        import torch
+        out = torch.empty(n, dtype=torch.int32, device=f"cuda:{self.device}")
+        self._bind_stream()
+        self._check(library().plas_stage_bijection(self._h, n, _u64x4(round_keys),
+                                                   ctypes.c_void_p(out.data_ptr())),
+                    "plas_stage_bijection")
+        return out
+
+
+@dataclass
+class SortResult:
+    reorders: int
+    levels: int
+    energy_fixed: int
+    scale_shift: int
+    energy: float
+    trace: list = field(default_factory=list)
+    blur_ms: float = 0.0
+    blur_launches: int = 0
+    assign_ms: float = 0.0
+    assign_launches: int = 0
+    total_ms: float = 0.0
+
+
+def _check_tensor(t, dtype):
+    if not t.is_cuda:
+        raise ValueError("expected a device (cuda) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+
+
+_contexts: dict[int, Context] = {}
+
+
+def context(device: int = 0) -> Context:
+    if device not in _contexts:
+        _contexts[device] = Context(device)
+    return _contexts[device]
+
+
+def sort(features, side: int | None = None, seed: int = 0x5EED, layout: str = "cn", **kw):
+    """Module-level shortcut of Context.sort on the tensor's device."""
+    return context(features.device.index or 0).sort(features, side, seed, layout, **kw)
+
+
+def grid_energy(features, perm=None, side: int | None = None, radius: int = 1, layout: str = "cn"):
+    return context(features.device.index or 0).grid_energy(features, perm, side, radius, layout)

@@ -1,0 +1,70 @@
+// plas_device.h -- data shared by the PLAS kernels and the host engine.
+#pragma once
+
+#include <stdint.h>
+
+namespace plas {
+
+// Number of separate energy accumulators the assignment kernel spreads its
+// atomics over (the controller adds them up).
+constexpr int kAccSlots = 32;
+
+// One radius level, prepared on the host (Sec. 3.1): real radius phi, blur
+// half-width r = floor(phi), block side beta = clamp(r + 1, min_block, w),
+// nb = floor(w / beta) blocks per side, floor(beta^2 / 4) groups per block.
+struct LevelInfo {
+  double phi;
+  int32_t r;
+  int32_t beta;
+  int32_t nb;
+  int32_t pad;
+  int64_t groups_per_block;
+  int64_t groups;   // nb^2 * groups_per_block
+  int64_t singles;  // cells in no group: w^2 - (nb*beta)^2 + nb^2 * (beta^2 mod 4)
+};
+
+// Device-resident state of one sort. The parameters block is what every
+// kernel of a reorder reads; the control block is owned by the controller
+// kernel, which runs once after each reorder.
+struct DevState {
+  // ---- parameters of the current reorder
+  int32_t done;
+  int32_t w;
+  int32_t r;
+  int32_t beta;
+  int32_t nb;
+  int32_t dy;
+  int32_t dx;
+  int32_t s;  // energy scale shift
+  int64_t groups_per_block;
+  int64_t groups;
+  int64_t singles;
+  uint64_t keys[4];  // round keys of the grouping bijection
+  // ---- written by the assignment kernel
+  unsigned long long energy_acc[kAccSlots];
+  unsigned long long moved_acc[kAccSlots];
+  // ---- control
+  int32_t level;
+  int32_t nlevels;
+  int32_t has_prev;
+  int32_t just_shifted;
+  int32_t levels_run;
+  uint32_t inv_threshold;
+  int64_t k;  // reorders done
+  int64_t max_reorders;
+  int64_t level_reorders;
+  uint64_t j;  // shift draws done
+  uint64_t seed;
+  uint64_t energy_prev;
+  uint64_t energy_last;
+  uint64_t level_moved;
+};
+
+// Small status block copied to pinned host memory at each sync.
+struct HostStatus {
+  int32_t done;
+  int32_t pad;
+  int64_t k;
+};
+
+}  // namespace plas

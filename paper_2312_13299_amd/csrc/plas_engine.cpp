@@ -1,0 +1,712 @@
+// plas_engine.cpp -- host side of libplas.so: argument checks, the device
+// workspace, the schedule, the launch sequence of a sort, and the C ABI of
+// include/plas.h and include/plas_stages.h.
+//
+// A sort runs entirely on the device. The host prepares the radius schedule
+// (it depends only on the grid side), uploads the first reorder's
+// parameters, and then queues reorders in chunks: blur rows, blur columns,
+// grouping table, assignment, controller. The controller kernel owns the
+// data-dependent control flow (stall test, new block shift, next radius), so
+// the host only reads a small status block between chunks to learn whether
+// the device has finished; kernels queued after the end return at once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "plas.h"
+#include "plas_device.h"
+#include "plas_launch.h"
+#include "plas_random.h"
+#include "plas_stages.h"
+
+using plas::DevState;
+using plas::HostStatus;
+using plas::LevelInfo;
+using plas::plas_level_out;
+
+static_assert(sizeof(plas_level_out) == sizeof(plas_level_stat), "trace entry layout");
+
+namespace {
+
+constexpr int kDefaultReordersPerSync = 32;
+
+struct DeviceBuffer {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct plas_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string error;
+  // Device workspace, grown on demand and kept.
+  DeviceBuffer grid_g, grid_h, grid_t;  // [n][dp] float32 each
+  DeviceBuffer perm;                    // int32[n]
+  DeviceBuffer table;                   // int32[beta^2]
+  DeviceBuffer inv;                     // float32 1/c, c = 0..w
+  DeviceBuffer range_part, range_out;   // range pass scratch and result
+  DeviceBuffer levels;                  // LevelInfo[levels]
+  DeviceBuffer trace;                   // plas_level_out[levels]
+  DeviceBuffer state;                   // DevState of a sort
+  DeviceBuffer stage_state;             // DevState of a stage call
+  DeviceBuffer scratch;                 // u64 accumulators and flags
+  // Pinned host memory for small read-backs.
+  HostStatus* status_host = nullptr;
+  float* range_host = nullptr;
+  unsigned long long* u64_host = nullptr;
+  DevState* state_host = nullptr;
+  std::vector<hipEvent_t> events;
+};
+
+namespace {
+
+// ---------------------------------------------------------------- helpers
+
+int32_t fail(plas_context* h, int32_t status, const std::string& msg) {
+  if (h != nullptr) h->error = msg;
+  return status;
+}
+
+int32_t hip_fail(plas_context* h, hipError_t e, const char* what) {
+  std::string msg = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    return fail(h, PLAS_ERR_OUT_OF_MEMORY, msg);
+  return fail(h, PLAS_ERR_HIP, msg);
+}
+
+#define PLAS_HIP(h, call)                                  \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return hip_fail((h), e_, #call); \
+  } while (0)
+
+// Keeps the caller's current device and restores it on exit.
+class DeviceScope {
+ public:
+  explicit DeviceScope(int device) {
+    if (hipGetDevice(&saved_) != hipSuccess) saved_ = -1;
+    ok_ = hipSetDevice(device) == hipSuccess;
+  }
+  ~DeviceScope() {
+    if (saved_ >= 0) (void)hipSetDevice(saved_);
+  }
+  bool ok() const { return ok_; }
+
+ private:
+  int saved_ = -1;
+  bool ok_ = false;
+};
+
+hipError_t reserve(DeviceBuffer& b, size_t bytes) {
+  if (bytes <= b.bytes && b.ptr != nullptr) return hipSuccess;
+  if (b.ptr != nullptr) {
+    hipError_t e = hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipMalloc(&b.ptr, bytes);
+  if (e != hipSuccess) {
+    b.ptr = nullptr;
+    return e;
+  }
+  b.bytes = bytes;
+  return hipSuccess;
+}
+
+void release(DeviceBuffer& b) {
+  if (b.ptr != nullptr) (void)hipFree(b.ptr);
+  b.ptr = nullptr;
+  b.bytes = 0;
+}
+
+template <typename T>
+T* as(DeviceBuffer& b) {
+  return static_cast<T*>(b.ptr);
+}
+
+int padded_channels(int d) {
+  int dp = 4;
+  while (dp < d) dp *= 2;
+  return dp;
+}
+
+// The radius schedule of Sec. 3.1 with the block geometry of each level.
+int32_t build_schedule(int32_t w, double decay, int32_t min_block, double start_radius,
+                       std::vector<LevelInfo>* out) {
+  if (w < 1 || !(decay > 0.0 && decay < 1.0) || min_block < 1) return PLAS_ERR_INVALID_ARGUMENT;
+  double phi = start_radius > 0.0 ? start_radius : static_cast<double>(w) / 2.0 - 1.0;
+  if (!(phi >= 1.0)) phi = 1.0;  // also catches NaN
+  out->clear();
+  while (phi >= 1.0) {
+    LevelInfo lv{};
+    lv.phi = phi;
+    // r beyond w - 1 blurs whole lines; the cap only keeps x + r in range.
+    const double rf = std::floor(phi);
+    lv.r = rf > 1073741824.0 ? 1073741824 : static_cast<int32_t>(rf);
+    lv.beta = std::min(w, std::max(min_block, lv.r + 1));
+    lv.nb = w / lv.beta;
+    const int64_t cells = static_cast<int64_t>(lv.beta) * lv.beta;
+    lv.groups_per_block = cells / 4;
+    lv.groups = static_cast<int64_t>(lv.nb) * lv.nb * lv.groups_per_block;
+    const int64_t covered = static_cast<int64_t>(lv.nb) * lv.beta;
+    lv.singles = static_cast<int64_t>(w) * w - covered * covered +
+                 static_cast<int64_t>(lv.nb) * lv.nb * (cells % 4);
+    out->push_back(lv);
+    phi = phi * decay;
+  }
+  return PLAS_OK;
+}
+
+int32_t scale_shift(const float* mins, const float* maxs, int32_t d, int64_t n) {
+  double dmax = 0.0;
+  for (int32_t c = 0; c < d; ++c) {
+    const double span = static_cast<double>(maxs[c]) - static_cast<double>(mins[c]);
+    dmax += span * span;
+  }
+  if (!(dmax > 0.0)) return 0;
+  int e = 0;
+  (void)std::frexp(static_cast<double>(n) * dmax, &e);
+  return 61 - e;
+}
+
+bool valid_layout(int32_t layout) { return layout == PLAS_LAYOUT_CN || layout == PLAS_LAYOUT_NC; }
+
+// Shared argument checks of plas_sort and plas_grid_energy.
+int32_t check_features(plas_context* h, const void* features, int64_t n, int32_t d, int32_t side,
+                       int32_t layout, int32_t dtype) {
+  if (h == nullptr) return PLAS_ERR_INVALID_ARGUMENT;
+  if (features == nullptr) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "features is NULL");
+  if (side < 2 || side > 46340) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "side must be in [2, 46340]");
+  if (n != static_cast<int64_t>(side) * side)
+    return fail(h, PLAS_ERR_INVALID_ARGUMENT, "n must equal side * side");
+  if (d < 1) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "d must be >= 1");
+  if (!valid_layout(layout)) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "unknown layout");
+  if (dtype == PLAS_DTYPE_BF16) return fail(h, PLAS_ERR_UNSUPPORTED, "bf16 features are not built yet");
+  if (dtype != PLAS_DTYPE_F32) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "unknown dtype");
+  if (d > PLAS_MAX_CHANNELS)
+    return fail(h, PLAS_ERR_UNSUPPORTED, "d above PLAS_MAX_CHANNELS is not supported");
+  return PLAS_OK;
+}
+
+// Ingest + range + scale shift, leaving X (cell-major padded features) in
+// grid_t. Returns NONFINITE if a value is not finite.
+int32_t prepare_features(plas_context* h, const float* features, int64_t n, int32_t d, int32_t layout,
+                         int dp, int32_t* s_out) {
+  const size_t grid_bytes = static_cast<size_t>(n) * dp * sizeof(float);
+  PLAS_HIP(h, reserve(h->grid_g, grid_bytes));
+  PLAS_HIP(h, reserve(h->grid_h, grid_bytes));
+  PLAS_HIP(h, reserve(h->grid_t, grid_bytes));
+  PLAS_HIP(h, reserve(h->range_part, plas::range_partial_floats(dp) * sizeof(float)));
+  PLAS_HIP(h, reserve(h->range_out, (2 * 64 + 1) * sizeof(float)));
+  float* X = as<float>(h->grid_t);
+  PLAS_HIP(h, plas::launch_ingest(features, n, d, layout, dp, X, h->stream));
+  PLAS_HIP(h, plas::launch_range(X, n, d, dp, as<float>(h->range_part), as<float>(h->range_out), h->stream));
+  PLAS_HIP(h, hipMemcpyAsync(h->range_host, h->range_out.ptr, (2 * dp + 1) * sizeof(float),
+                             hipMemcpyDeviceToHost, h->stream));
+  PLAS_HIP(h, hipStreamSynchronize(h->stream));
+  if (h->range_host[2 * dp] != 0.0f)
+    return fail(h, PLAS_ERR_NONFINITE, "features contain NaN or infinity");
+  *s_out = scale_shift(h->range_host, h->range_host + dp, d, n);
+  return PLAS_OK;
+}
+
+// Validate a caller permutation (device int32[n]); uses grid_h as scratch.
+int32_t check_permutation(plas_context* h, const int32_t* perm, int64_t n) {
+  int32_t* counts = as<int32_t>(h->grid_h);
+  int32_t* flag = reinterpret_cast<int32_t*>(as<unsigned long long>(h->scratch) + 8);
+  PLAS_HIP(h, hipMemsetAsync(counts, 0, static_cast<size_t>(n) * sizeof(int32_t), h->stream));
+  PLAS_HIP(h, hipMemsetAsync(flag, 0, sizeof(int32_t), h->stream));
+  PLAS_HIP(h, plas::launch_check_perm(perm, n, counts, flag, h->stream));
+  PLAS_HIP(h, hipMemcpyAsync(h->u64_host, flag, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+  PLAS_HIP(h, hipStreamSynchronize(h->stream));
+  int32_t bad = 0;
+  std::memcpy(&bad, h->u64_host, sizeof(int32_t));
+  if (bad != 0) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "permutation is not a bijection of [0, n)");
+  return PLAS_OK;
+}
+
+int32_t upload_inverse_counts(plas_context* h, int32_t w) {
+  PLAS_HIP(h, reserve(h->inv, static_cast<size_t>(w + 1) * sizeof(float)));
+  std::vector<float> inv(static_cast<size_t>(w) + 1);
+  inv[0] = 0.0f;
+  for (int32_t c = 1; c <= w; ++c) inv[c] = 1.0f / static_cast<float>(c);
+  PLAS_HIP(h, hipMemcpyAsync(h->inv.ptr, inv.data(), inv.size() * sizeof(float), hipMemcpyHostToDevice,
+                             h->stream));
+  // The source vector dies at return; make the copy complete first.
+  PLAS_HIP(h, hipStreamSynchronize(h->stream));
+  return PLAS_OK;
+}
+
+int32_t ensure_events(plas_context* h, size_t count) {
+  while (h->events.size() < count) {
+    hipEvent_t e;
+    PLAS_HIP(h, hipEventCreate(&e));
+    h->events.push_back(e);
+  }
+  return PLAS_OK;
+}
+
+void fill_state_for_level(DevState* s, const LevelInfo& lv) {
+  s->r = lv.r;
+  s->beta = lv.beta;
+  s->nb = lv.nb;
+  s->groups_per_block = lv.groups_per_block;
+  s->groups = lv.groups;
+  s->singles = lv.singles;
+}
+
+}  // namespace
+
+// ======================================================================== C ABI
+
+extern "C" {
+
+int32_t plas_get_abi_version(void) { return PLAS_ABI_VERSION; }
+
+int32_t plas_sort_params_init(plas_sort_params* p) {
+  if (p == nullptr) return PLAS_ERR_INVALID_ARGUMENT;
+  std::memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(plas_sort_params);
+  p->inv_threshold = 10000;
+  p->seed = 0x5EED;
+  p->radius_decay = 0.95;
+  p->start_radius = 0.0;
+  p->max_reorders = 0;
+  p->init_perm = nullptr;
+  p->min_block = 16;
+  p->profile = 0;
+  p->reorders_per_sync = 0;
+  return PLAS_OK;
+}
+
+const char* plas_status_string(int32_t status) {
+  switch (status) {
+    case PLAS_OK: return "ok";
+    case PLAS_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case PLAS_ERR_UNSUPPORTED: return "unsupported";
+    case PLAS_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case PLAS_ERR_HIP: return "HIP runtime error";
+    case PLAS_ERR_NONFINITE: return "non-finite feature value";
+    default: return "unknown status";
+  }
+}
+
+const char* plas_last_error(plas_handle h) { return h == nullptr ? "" : h->error.c_str(); }
+
+int32_t plas_create(plas_handle* out, int32_t device) {
+  if (out == nullptr) return PLAS_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return PLAS_ERR_HIP;
+  if (device < 0 || device >= count) return PLAS_ERR_INVALID_ARGUMENT;
+  plas_context* h = new (std::nothrow) plas_context();
+  if (h == nullptr) return PLAS_ERR_OUT_OF_MEMORY;
+  h->device = device;
+  DeviceScope scope(device);
+  if (!scope.ok()) {
+    delete h;
+    return PLAS_ERR_HIP;
+  }
+  bool ok = hipHostMalloc(reinterpret_cast<void**>(&h->status_host), sizeof(HostStatus)) == hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&h->range_host), (2 * 64 + 1) * sizeof(float)) == hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&h->u64_host), 16 * sizeof(unsigned long long)) == hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&h->state_host), sizeof(DevState)) == hipSuccess &&
+            reserve(h->state, sizeof(DevState)) == hipSuccess &&
+            reserve(h->stage_state, sizeof(DevState)) == hipSuccess &&
+            reserve(h->scratch, 16 * sizeof(unsigned long long)) == hipSuccess;
+  if (!ok) {
+    plas_destroy(h);
+    return PLAS_ERR_OUT_OF_MEMORY;
+  }
+  *out = h;
+  return PLAS_OK;
+}
+
+int32_t plas_destroy(plas_handle h) {
+  if (h == nullptr) return PLAS_OK;
+  DeviceScope scope(h->device);
+  if (h->stream != nullptr) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+  DeviceBuffer* bufs[] = {&h->grid_g, &h->grid_h, &h->grid_t, &h->perm, &h->table, &h->inv,
+                          &h->range_part, &h->range_out, &h->levels, &h->trace, &h->state,
+                          &h->stage_state, &h->scratch};
+  for (DeviceBuffer* b : bufs) release(*b);
+  if (h->status_host) (void)hipHostFree(h->status_host);
+  if (h->range_host) (void)hipHostFree(h->range_host);
+  if (h->u64_host) (void)hipHostFree(h->u64_host);
+  if (h->state_host) (void)hipHostFree(h->state_host);
+  delete h;
+  return PLAS_OK;
+}
+
+int32_t plas_set_stream(plas_handle h, void* stream) {
+  if (h == nullptr) return PLAS_ERR_INVALID_ARGUMENT;
+  h->stream = static_cast<hipStream_t>(stream);
+  return PLAS_OK;
+}
+
+int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int32_t side,
+                  int32_t layout, int32_t dtype, const plas_sort_params* params, int32_t* perm_out,
+                  plas_sort_stats* stats) {
+  const auto t_start = std::chrono::steady_clock::now();
+  int32_t st = check_features(h, features, n, d, side, layout, dtype);
+  if (st != PLAS_OK) return st;
+  h->error.clear();
+  if (perm_out == nullptr) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "perm_out is NULL");
+  plas_sort_params prm;
+  plas_sort_params_init(&prm);
+  if (params != nullptr) {
+    if (params->struct_size != sizeof(plas_sort_params))
+      return fail(h, PLAS_ERR_INVALID_ARGUMENT, "params->struct_size does not match this library");
+    prm = *params;
+  }
+  if (!(prm.radius_decay > 0.0 && prm.radius_decay < 1.0))
+    return fail(h, PLAS_ERR_INVALID_ARGUMENT, "radius_decay must be in (0, 1)");
+  if (prm.inv_threshold < 1) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "inv_threshold must be >= 1");
+  if (prm.min_block < 1) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "min_block must be >= 1");
+  if (prm.max_reorders < 0) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "max_reorders must be >= 0");
+  if (stats != nullptr && stats->struct_size != sizeof(plas_sort_stats))
+    return fail(h, PLAS_ERR_INVALID_ARGUMENT, "stats->struct_size does not match this library");
+
+  DeviceScope scope(h->device);
+  if (!scope.ok()) return fail(h, PLAS_ERR_HIP, "hipSetDevice failed");
+  const int32_t w = side;
+  const int dp = padded_channels(d);
+
+  std::vector<LevelInfo> levels;
+  st = build_schedule(w, prm.radius_decay, prm.min_block, prm.start_radius, &levels);
+  if (st != PLAS_OK) return fail(h, st, "bad schedule parameters");
+  int64_t max_cells = 0, max_items = 0;
+  for (const LevelInfo& lv : levels) {
+    max_cells = std::max<int64_t>(max_cells, static_cast<int64_t>(lv.beta) * lv.beta);
+    max_items = std::max<int64_t>(max_items, lv.groups + lv.singles);
+  }
+
+  // Workspace.
+  int32_t s = 0;
+  st = prepare_features(h, static_cast<const float*>(features), n, d, layout, dp, &s);
+  if (st != PLAS_OK) return st;
+  PLAS_HIP(h, reserve(h->perm, static_cast<size_t>(n) * sizeof(int32_t)));
+  PLAS_HIP(h, reserve(h->table, static_cast<size_t>(max_cells) * sizeof(int32_t)));
+  PLAS_HIP(h, reserve(h->levels, levels.size() * sizeof(LevelInfo)));
+  PLAS_HIP(h, reserve(h->trace, levels.size() * sizeof(plas_level_out)));
+  st = upload_inverse_counts(h, w);
+  if (st != PLAS_OK) return st;
+  PLAS_HIP(h, hipMemcpyAsync(h->levels.ptr, levels.data(), levels.size() * sizeof(LevelInfo),
+                             hipMemcpyHostToDevice, h->stream));
+  PLAS_HIP(h, hipMemsetAsync(h->trace.ptr, 0, levels.size() * sizeof(plas_level_out), h->stream));
+
+  float* G = as<float>(h->grid_g);
+  float* H = as<float>(h->grid_h);
+  float* T = as<float>(h->grid_t);  // holds X until the gather
+  int32_t* P = as<int32_t>(h->perm);
+
+  // Start arrangement: the caller's, or the keyed bijection of draw
+  // (seed, 0, 0) (random positions, Sec. 3.1).
+  if (prm.init_perm != nullptr) {
+    st = check_permutation(h, prm.init_perm, n);
+    if (st != PLAS_OK) return st;
+    PLAS_HIP(h, hipMemcpyAsync(P, prm.init_perm, static_cast<size_t>(n) * sizeof(int32_t),
+                               hipMemcpyDeviceToDevice, h->stream));
+  } else {
+    const plas::Words4 k0 = plas::draw(prm.seed, plas::kDrawStart, 0);
+    PLAS_HIP(h, plas::launch_start_perm(P, n, k0.v, h->stream));
+  }
+  PLAS_HIP(h, plas::launch_gather(T, P, G, n, dp, h->stream));
+
+  // First reorder's state.
+  DevState* S = h->state_host;
+  std::memset(S, 0, sizeof(DevState));
+  S->w = w;
+  S->s = s;
+  fill_state_for_level(S, levels[0]);
+  S->nlevels = static_cast<int32_t>(levels.size());
+  S->inv_threshold = prm.inv_threshold;
+  S->max_reorders = prm.max_reorders;
+  S->seed = prm.seed;
+  plas::block_shift(prm.seed, 0, w, &S->dy, &S->dx);
+  S->j = 1;
+  const plas::Words4 keys = plas::draw(prm.seed, plas::kDrawGrouping, 0);
+  for (int i = 0; i < 4; ++i) S->keys[i] = keys.v[i];
+  DevState* Sd = as<DevState>(h->state);
+  PLAS_HIP(h, hipMemcpyAsync(Sd, S, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
+
+  const LevelInfo* Ld = as<LevelInfo>(h->levels);
+  plas_level_out* Td = as<plas_level_out>(h->trace);
+  const int32_t* table = as<int32_t>(h->table);
+  const int chunk = prm.reorders_per_sync > 0 ? prm.reorders_per_sync : kDefaultReordersPerSync;
+  const bool profile = prm.profile != 0;
+  if (profile) {
+    st = ensure_events(h, static_cast<size_t>(chunk) * 4);
+    if (st != PLAS_OK) return st;
+  }
+  // Improvements per level are at most about M * ln(2^62); two stalls end it.
+  const int64_t reorder_bound =
+      static_cast<int64_t>(levels.size()) * (static_cast<int64_t>(prm.inv_threshold) * 44 + 3);
+  double blur_ms = 0.0, assign_ms = 0.0;
+  int64_t timed_reorders = 0;
+  int64_t k_seen = 0;
+  for (;;) {
+    for (int i = 0; i < chunk; ++i) {
+      if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 0], h->stream));
+      PLAS_HIP(h, plas::launch_blur_pass(G, H, w, dp, Sd, 0, 0, as<float>(h->inv), h->stream));
+      PLAS_HIP(h, plas::launch_blur_pass(H, T, w, dp, Sd, 0, 1, as<float>(h->inv), h->stream));
+      if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 1], h->stream));
+      PLAS_HIP(h, plas::launch_group_table(as<int32_t>(h->table), Sd, max_cells, h->stream));
+      if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 2], h->stream));
+      PLAS_HIP(h, plas::launch_assign(G, T, P, table, Sd, dp, max_items, h->stream));
+      if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 3], h->stream));
+      PLAS_HIP(h, plas::launch_control(Sd, Ld, Td, h->stream));
+    }
+    PLAS_HIP(h, hipMemcpyAsync(h->status_host, &Sd->done, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    PLAS_HIP(h, hipMemcpyAsync(&h->status_host->k, &Sd->k, sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
+    PLAS_HIP(h, hipStreamSynchronize(h->stream));
+    if (profile) {
+      // Only the reorders that ran count; the rest of the chunk returned at once.
+      const int64_t ran = std::min<int64_t>(chunk, h->status_host->k - k_seen);
+      for (int64_t i = 0; i < ran; ++i) {
+        float a = 0.0f, b = 0.0f;
+        PLAS_HIP(h, hipEventElapsedTime(&a, h->events[4 * i + 0], h->events[4 * i + 1]));
+        PLAS_HIP(h, hipEventElapsedTime(&b, h->events[4 * i + 2], h->events[4 * i + 3]));
+        blur_ms += a;
+        assign_ms += b;
+      }
+      timed_reorders += ran;
+    }
+    if (h->status_host->done) break;
+    // Each queued reorder either runs (k grows) or finds the sort done, so a
+    // chunk that leaves k unchanged without done means the device state is
+    // broken; also stop at the bound on reorders that the stall test implies
+    // (energies strictly fall by at least 1/M per improvement).
+    if (h->status_host->k == k_seen || h->status_host->k > reorder_bound)
+      return fail(h, PLAS_ERR_HIP, "device controller made no progress");
+    k_seen = h->status_host->k;
+  }
+
+  PLAS_HIP(h, hipMemcpyAsync(perm_out, P, static_cast<size_t>(n) * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                             h->stream));
+  PLAS_HIP(h, hipMemcpyAsync(S, Sd, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+  PLAS_HIP(h, hipStreamSynchronize(h->stream));
+  if (stats != nullptr) {
+    stats->levels = S->levels_run;
+    stats->reorders = S->k;
+    stats->energy_fixed = S->energy_last;
+    stats->scale_shift = s;
+    stats->energy = std::ldexp(static_cast<double>(S->energy_last), -s) / static_cast<double>(n);
+    stats->trace_len = 0;
+    if (stats->trace != nullptr && stats->trace_cap > 0) {
+      const int32_t len = std::min(stats->trace_cap, S->levels_run);
+      if (len > 0) {
+        PLAS_HIP(h, hipMemcpyAsync(stats->trace, Td, static_cast<size_t>(len) * sizeof(plas_level_out),
+                                   hipMemcpyDeviceToHost, h->stream));
+        PLAS_HIP(h, hipStreamSynchronize(h->stream));
+      }
+      stats->trace_len = len;
+    }
+    stats->blur_ms = blur_ms;
+    stats->blur_launches = 2 * timed_reorders;
+    stats->assign_ms = assign_ms;
+    stats->assign_launches = timed_reorders;
+    stats->total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  return PLAS_OK;
+}
+
+int32_t plas_grid_energy(plas_handle h, const void* features, const int32_t* perm, int64_t n, int32_t d,
+                         int32_t side, int32_t layout, int32_t dtype, int32_t radius, uint64_t* energy_fixed,
+                         int32_t* scale_shift_out, double* energy_mean) {
+  int32_t st = check_features(h, features, n, d, side, layout, dtype);
+  if (st != PLAS_OK) return st;
+  h->error.clear();
+  if (radius < 0) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "radius must be >= 0");
+  DeviceScope scope(h->device);
+  if (!scope.ok()) return fail(h, PLAS_ERR_HIP, "hipSetDevice failed");
+  const int dp = padded_channels(d);
+  int32_t s = 0;
+  st = prepare_features(h, static_cast<const float*>(features), n, d, layout, dp, &s);
+  if (st != PLAS_OK) return st;
+  if (perm != nullptr) {
+    st = check_permutation(h, perm, n);
+    if (st != PLAS_OK) return st;
+  }
+  st = upload_inverse_counts(h, side);
+  if (st != PLAS_OK) return st;
+  float* G = as<float>(h->grid_g);
+  float* H = as<float>(h->grid_h);
+  float* T = as<float>(h->grid_t);
+  PLAS_HIP(h, plas::launch_gather(T, perm, G, n, dp, h->stream));
+  PLAS_HIP(h, plas::launch_blur_pass(G, H, side, dp, nullptr, radius, 0, as<float>(h->inv), h->stream));
+  PLAS_HIP(h, plas::launch_blur_pass(H, T, side, dp, nullptr, radius, 1, as<float>(h->inv), h->stream));
+  unsigned long long* acc = as<unsigned long long>(h->scratch);
+  PLAS_HIP(h, hipMemsetAsync(acc, 0, sizeof(unsigned long long), h->stream));
+  PLAS_HIP(h, plas::launch_energy(G, T, n, dp, s, acc, h->stream));
+  PLAS_HIP(h, hipMemcpyAsync(h->u64_host, acc, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
+  PLAS_HIP(h, hipStreamSynchronize(h->stream));
+  const uint64_t E = h->u64_host[0];
+  if (energy_fixed) *energy_fixed = E;
+  if (scale_shift_out) *scale_shift_out = s;
+  if (energy_mean) *energy_mean = std::ldexp(static_cast<double>(E), -s) / static_cast<double>(n);
+  return PLAS_OK;
+}
+
+// ------------------------------------------------------------------ stages
+
+static bool valid_dp(int32_t dp) { return dp == 4 || dp == 8 || dp == 16 || dp == 32 || dp == 64; }
+
+int32_t plas_stage_blur(plas_handle h, const float* grid, float* target, int32_t side, int32_t dp,
+                        int32_t radius) {
+  if (h == nullptr) return PLAS_ERR_INVALID_ARGUMENT;
+  if (grid == nullptr || target == nullptr || side < 1 || side > 46340 || !valid_dp(dp) || radius < 0)
+    return fail(h, PLAS_ERR_INVALID_ARGUMENT, "bad blur arguments");
+  DeviceScope scope(h->device);
+  const int64_t n = static_cast<int64_t>(side) * side;
+  PLAS_HIP(h, reserve(h->grid_h, static_cast<size_t>(n) * dp * sizeof(float)));
+  int32_t st = upload_inverse_counts(h, side);
+  if (st != PLAS_OK) return st;
+  float* H = as<float>(h->grid_h);
+  PLAS_HIP(h, plas::launch_blur_pass(grid, H, side, dp, nullptr, radius, 0, as<float>(h->inv), h->stream));
+  PLAS_HIP(h, plas::launch_blur_pass(H, target, side, dp, nullptr, radius, 1, as<float>(h->inv), h->stream));
+  PLAS_HIP(h, hipStreamSynchronize(h->stream));
+  return PLAS_OK;
+}
+
+static int32_t upload_stage_state(plas_handle h, int32_t side, int32_t beta, int32_t dy, int32_t dx,
+                                  const uint64_t keys[4], int32_t s) {
+  DevState* S = h->state_host;
+  std::memset(S, 0, sizeof(DevState));
+  S->w = side;
+  S->s = s;
+  S->dy = dy;
+  S->dx = dx;
+  LevelInfo lv{};
+  lv.phi = static_cast<double>(beta - 1);
+  lv.r = beta - 1;
+  lv.beta = beta;
+  lv.nb = side / beta;
+  const int64_t cells = static_cast<int64_t>(beta) * beta;
+  lv.groups_per_block = cells / 4;
+  lv.groups = static_cast<int64_t>(lv.nb) * lv.nb * lv.groups_per_block;
+  const int64_t covered = static_cast<int64_t>(lv.nb) * beta;
+  lv.singles = static_cast<int64_t>(side) * side - covered * covered +
+               static_cast<int64_t>(lv.nb) * lv.nb * (cells % 4);
+  fill_state_for_level(S, lv);
+  for (int i = 0; i < 4; ++i) S->keys[i] = keys[i];
+  PLAS_HIP(h, hipMemcpyAsync(h->stage_state.ptr, S, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
+  PLAS_HIP(h, hipStreamSynchronize(h->stream));
+  return PLAS_OK;
+}
+
+int32_t plas_stage_group_table(plas_handle h, int32_t beta, const uint64_t round_keys[4], int32_t* table) {
+  if (h == nullptr) return PLAS_ERR_INVALID_ARGUMENT;
+  if (table == nullptr || round_keys == nullptr || beta < 1 || beta > 65535)
+    return fail(h, PLAS_ERR_INVALID_ARGUMENT, "bad group table arguments");
+  DeviceScope scope(h->device);
+  int32_t st = upload_stage_state(h, beta, beta, 0, 0, round_keys, 0);
+  if (st != PLAS_OK) return st;
+  PLAS_HIP(h, plas::launch_group_table(table, as<DevState>(h->stage_state),
+                                       static_cast<int64_t>(beta) * beta, h->stream));
+  PLAS_HIP(h, hipStreamSynchronize(h->stream));
+  return PLAS_OK;
+}
+
+int32_t plas_stage_assign(plas_handle h, float* grid, const float* target, int32_t* perm, int32_t side,
+                          int32_t dp, int32_t beta, int32_t dy, int32_t dx, const uint64_t round_keys[4],
+                          int32_t scale_shift_in, uint64_t* energy, uint64_t* moved) {
+  if (h == nullptr) return PLAS_ERR_INVALID_ARGUMENT;
+  if (grid == nullptr || target == nullptr || perm == nullptr || round_keys == nullptr || side < 2 ||
+      side > 46340 || !valid_dp(dp) || beta < 2 || beta > side || dy < 0 || dy >= side || dx < 0 ||
+      dx >= side)
+    return fail(h, PLAS_ERR_INVALID_ARGUMENT, "bad assign arguments");
+  DeviceScope scope(h->device);
+  const int64_t cells = static_cast<int64_t>(beta) * beta;
+  PLAS_HIP(h, reserve(h->table, static_cast<size_t>(cells) * sizeof(int32_t)));
+  int32_t st = upload_stage_state(h, side, beta, dy, dx, round_keys, scale_shift_in);
+  if (st != PLAS_OK) return st;
+  DevState* Sd = as<DevState>(h->stage_state);
+  PLAS_HIP(h, plas::launch_group_table(as<int32_t>(h->table), Sd, cells, h->stream));
+  const int64_t items = h->state_host->groups + h->state_host->singles;
+  PLAS_HIP(h, plas::launch_assign(grid, target, perm, as<int32_t>(h->table), Sd, dp, items, h->stream));
+  PLAS_HIP(h, hipMemcpyAsync(h->state_host, Sd, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+  PLAS_HIP(h, hipStreamSynchronize(h->stream));
+  unsigned long long E = 0, M = 0;
+  for (int i = 0; i < plas::kAccSlots; ++i) {
+    E += h->state_host->energy_acc[i];
+    M += h->state_host->moved_acc[i];
+  }
+  if (energy) *energy = E;
+  if (moved) *moved = M;
+  return PLAS_OK;
+}
+
+int32_t plas_stage_energy(plas_handle h, const float* grid, const float* target, int32_t side, int32_t dp,
+                          int32_t scale_shift_in, uint64_t* energy) {
+  if (h == nullptr) return PLAS_ERR_INVALID_ARGUMENT;
+  if (grid == nullptr || target == nullptr || side < 1 || side > 46340 || !valid_dp(dp))
+    return fail(h, PLAS_ERR_INVALID_ARGUMENT, "bad energy arguments");
+  DeviceScope scope(h->device);
+  unsigned long long* acc = as<unsigned long long>(h->scratch);
+  PLAS_HIP(h, hipMemsetAsync(acc, 0, sizeof(unsigned long long), h->stream));
+  PLAS_HIP(h, plas::launch_energy(grid, target, static_cast<int64_t>(side) * side, dp, scale_shift_in, acc,
+                                  h->stream));
+  PLAS_HIP(h, hipMemcpyAsync(h->u64_host, acc, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
+  PLAS_HIP(h, hipStreamSynchronize(h->stream));
+  if (energy) *energy = h->u64_host[0];
+  return PLAS_OK;
+}
+
+int32_t plas_stage_bijection(plas_handle h, int64_t n, const uint64_t round_keys[4], int32_t* out) {
+  if (h == nullptr) return PLAS_ERR_INVALID_ARGUMENT;
+  if (out == nullptr || round_keys == nullptr || n < 1 || n > 2147483647LL)
+    return fail(h, PLAS_ERR_INVALID_ARGUMENT, "bad bijection arguments");
+  DeviceScope scope(h->device);
+  PLAS_HIP(h, plas::launch_start_perm(out, n, round_keys, h->stream));
+  PLAS_HIP(h, hipStreamSynchronize(h->stream));
+  return PLAS_OK;
+}
+
+void plas_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  plas::Words4 x;
+  for (int i = 0; i < 4; ++i) x.v[i] = ctr[i];
+  const plas::Words4 y = plas::philox4x64_10(x, key[0], key[1]);
+  for (int i = 0; i < 4; ++i) out[i] = y.v[i];
+}
+
+void plas_draw(uint64_t seed, uint64_t purpose, uint64_t index, uint64_t out[4]) {
+  const plas::Words4 y = plas::draw(seed, purpose, index);
+  for (int i = 0; i < 4; ++i) out[i] = y.v[i];
+}
+
+int32_t plas_schedule(int32_t side, double decay, int32_t min_block, double start_radius, double* phi,
+                      int32_t* r, int32_t* beta, int32_t cap) {
+  std::vector<LevelInfo> levels;
+  const int32_t st = build_schedule(side, decay, min_block, start_radius, &levels);
+  if (st != PLAS_OK) return st;
+  for (size_t i = 0; i < levels.size() && static_cast<int64_t>(i) < cap; ++i) {
+    if (phi) phi[i] = levels[i].phi;
+    if (r) r[i] = levels[i].r;
+    if (beta) beta[i] = levels[i].beta;
+  }
+  return static_cast<int32_t>(levels.size());
+}
+
+int32_t plas_scale_shift_from_ranges(const float* mins, const float* maxs, int32_t d, int64_t n,
+                                     int32_t* scale_shift_out) {
+  if (mins == nullptr || maxs == nullptr || d < 1 || n < 1 || scale_shift_out == nullptr)
+    return PLAS_ERR_INVALID_ARGUMENT;
+  *scale_shift_out = scale_shift(mins, maxs, d, n);
+  return PLAS_OK;
+}
+
+}  // extern "C"

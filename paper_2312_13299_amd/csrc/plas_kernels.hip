@@ -1,0 +1,616 @@
+// plas_kernels.hip -- gfx950 kernels of one PLAS sort (Sec. 3.1 of arXiv
+// 2312.13299): ingest, range, start arrangement, gather, separable box blur,
+// grouping table, blockwise assignment with its energy, and the controller.
+//
+// Working layout: a grid is float32 [n][DP], cell-major, DP a power of two
+// (4..64) with zero padding beyond the d real channels. A cell of DP = 64 is
+// 256 bytes, two full 128-byte cache lines, so the assignment kernel's random
+// cell reads waste nothing, and a blur line is read as whole cells.
+//
+// Floating point: compiled without contraction (-ffp-contract=off) and with
+// denormals kept, so every float operation below is one IEEE-rounded add,
+// subtract or multiply in the order written. That is what makes the results
+// equal, bit for bit, to a CPU that evaluates the same expressions.
+#include <hip/hip_runtime.h>
+
+#include "plas_launch.h"
+#include "plas_random.h"
+
+namespace plas {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kRangeBlocks = 256;
+constexpr int kMaxGridBlocks = 4096;
+
+inline int blocks_for(int64_t threads, int64_t cap = kMaxGridBlocks) {
+  int64_t b = (threads + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return static_cast<int>(b);
+}
+
+// ----------------------------------------------------------------- ingest
+
+// Channel-major [d][n] -> [n][DP]: a 64-cell tile goes through LDS so that
+// both the reads (64 consecutive cells of one channel) and the writes
+// (64 consecutive cells of DP channels) are contiguous.
+template <int DP>
+__global__ __launch_bounds__(kBlock) void k_ingest_cn(const float* __restrict__ F, int64_t n, int d,
+                                                      float* __restrict__ X) {
+  __shared__ float tile[DP][65];
+  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * 64;
+  for (int e = threadIdx.x; e < DP * 64; e += kBlock) {
+    const int c = e >> 6, i = e & 63;
+    const int64_t cell = n0 + i;
+    tile[c][i] = (c < d && cell < n) ? F[static_cast<int64_t>(c) * n + cell] : 0.0f;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < DP * 64; e += kBlock) {
+    const int i = e / DP, c = e % DP;
+    const int64_t cell = n0 + i;
+    if (cell < n) X[cell * DP + c] = tile[c][i];
+  }
+}
+
+template <int DP>
+__global__ __launch_bounds__(kBlock) void k_ingest_nc(const float* __restrict__ F, int64_t n, int d,
+                                                      float* __restrict__ X) {
+  const int64_t total = n * DP;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; e < total; e += stride) {
+    const int64_t cell = e / DP;
+    const int c = static_cast<int>(e % DP);
+    X[e] = c < d ? F[cell * d + c] : 0.0f;
+  }
+}
+
+// ------------------------------------------------------------------ range
+
+// Each thread owns one channel (the grid stride is a multiple of DP), so a
+// block reduces to DP partial min/max values in LDS.
+template <int DP>
+__global__ __launch_bounds__(kBlock) void k_range_partial(const float* __restrict__ X, int64_t n,
+                                                          float* __restrict__ part) {
+  __shared__ float s_lo[kBlock], s_hi[kBlock], s_bad[kBlock];
+  const int t = threadIdx.x;
+  float lo = INFINITY, hi = -INFINITY, bad = 0.0f;
+  const int64_t total = n * DP;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + t; e < total; e += stride) {
+    const float v = X[e];
+    if (!__builtin_isfinite(v)) bad = 1.0f;
+    lo = fminf(lo, v);
+    hi = fmaxf(hi, v);
+  }
+  s_lo[t] = lo;
+  s_hi[t] = hi;
+  s_bad[t] = bad;
+  __syncthreads();
+  for (int s = kBlock / 2; s >= DP; s >>= 1) {
+    if (t < s) {
+      s_lo[t] = fminf(s_lo[t], s_lo[t + s]);
+      s_hi[t] = fmaxf(s_hi[t], s_hi[t + s]);
+      s_bad[t] = fmaxf(s_bad[t], s_bad[t + s]);
+    }
+    __syncthreads();
+  }
+  if (t < DP) {
+    float* out = part + static_cast<int64_t>(blockIdx.x) * 3 * DP;
+    out[t] = s_lo[t];
+    out[DP + t] = s_hi[t];
+    out[2 * DP + t] = s_bad[t];
+  }
+}
+
+template <int DP>
+__global__ void k_range_finish(const float* __restrict__ part, int nparts, int d,
+                               float* __restrict__ out) {
+  // Launched with one wave of 64 threads; lanes c >= DP only join the barrier.
+  __shared__ float s_bad[64];
+  const int c = threadIdx.x;
+  float bad = 0.0f;
+  if (c < DP) {
+    float lo = INFINITY, hi = -INFINITY;
+    for (int b = 0; b < nparts; ++b) {
+      const float* p = part + static_cast<int64_t>(b) * 3 * DP;
+      lo = fminf(lo, p[c]);
+      hi = fmaxf(hi, p[DP + c]);
+      bad = fmaxf(bad, p[2 * DP + c]);
+    }
+    out[c] = lo;
+    out[DP + c] = hi;
+  }
+  // One flag for all real channels, reduced by lane 0 from the others.
+  s_bad[c] = c < d ? bad : 0.0f;
+  __syncthreads();
+  if (c == 0) {
+    float any = 0.0f;
+    for (int i = 0; i < DP; ++i) any = fmaxf(any, s_bad[i]);
+    out[2 * DP] = any;
+  }
+}
+
+// ------------------------------------------------- start arrangement, gather
+
+__global__ __launch_bounds__(kBlock) void k_start_perm(int32_t* __restrict__ P, int64_t n, Words4 keys) {
+  const Bijection f(static_cast<uint64_t>(n), keys.v);
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n; p += stride)
+    P[p] = static_cast<int32_t>(f(static_cast<uint64_t>(p)));
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_perm(const int32_t* __restrict__ init, int64_t n,
+                                                       int32_t* __restrict__ counts,
+                                                       int32_t* __restrict__ flag) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n; p += stride) {
+    const int32_t v = init[p];
+    if (v < 0 || v >= n)
+      atomicOr(flag, 1);
+    else
+      atomicAdd(&counts[v], 1);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_verify_counts(const int32_t* __restrict__ counts, int64_t n,
+                                                          int32_t* __restrict__ flag) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n; p += stride)
+    if (counts[p] != 1) atomicOr(flag, 1);
+}
+
+// G[p] = X[P[p]] (P NULL: identity), 16 bytes per thread.
+template <int DP>
+__global__ __launch_bounds__(kBlock) void k_gather(const float* __restrict__ X, const int32_t* __restrict__ P,
+                                                   float* __restrict__ G, int64_t n) {
+  constexpr int LG = DP / 4;
+  const float4* __restrict__ src = reinterpret_cast<const float4*>(X);
+  float4* __restrict__ dst = reinterpret_cast<float4*>(G);
+  const int64_t total = n * LG;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; e < total; e += stride) {
+    const int64_t p = e / LG;
+    const int j = static_cast<int>(e % LG);
+    const int64_t from = P != nullptr ? static_cast<int64_t>(P[p]) : p;
+    dst[e] = src[from * LG + j];
+  }
+}
+
+// ------------------------------------------------------------------- blur
+
+// One separable box-blur pass. Lane = (line, channel): DP consecutive lanes
+// walk one line, 64 / DP lines per wave. Along the line the window sum is
+// kept as a running sum: it starts as the ascending sum of the first
+// min(r, w-1) + 1 values; at each next position the entering value is added
+// and then the leaving value subtracted, and the output is the running sum
+// times float32(1 / count) for the window clipped to the grid.
+template <int DP>
+__global__ __launch_bounds__(kBlock) void k_blur(const float* __restrict__ in, float* __restrict__ out,
+                                                 int w, const DevState* __restrict__ st, int radius,
+                                                 int vertical, const float* __restrict__ inv) {
+  if (st != nullptr && st->done) return;
+  const int r = st != nullptr ? st->r : radius;
+  constexpr int LPW = 64 / DP;
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t line = wave * LPW + lane / DP;
+  const int c = lane % DP;
+  if (line >= w) return;
+  const int64_t base = vertical ? line * DP + c : line * w * DP + c;
+  const int64_t step = vertical ? static_cast<int64_t>(w) * DP : DP;
+  const float* __restrict__ src = in + base;
+  float* __restrict__ dst = out + base;
+  if (r == 0) {
+    for (int x = 0; x < w; ++x) dst[x * step] = src[x * step];
+    return;
+  }
+  const int first_hi = r < w - 1 ? r : w - 1;
+  float s = src[0];
+  for (int t = 1; t <= first_hi; ++t) s = s + src[t * step];
+  dst[0] = s * inv[first_hi + 1];
+  for (int x = 1; x < w; ++x) {
+    if (x + r <= w - 1) s = s + src[static_cast<int64_t>(x + r) * step];
+    if (x - r - 1 >= 0) s = s - src[static_cast<int64_t>(x - r - 1) * step];
+    const int hi = x + r < w - 1 ? x + r : w - 1;
+    const int lo = x - r > 0 ? x - r : 0;
+    dst[x * step] = s * inv[hi - lo + 1];
+  }
+}
+
+// ---------------------------------------------------------- group table
+
+// table[t] = pi(t) packed as (ly << 16) | lx, pi the grouping bijection of
+// the current reorder over the beta^2 block-local cells.
+__global__ __launch_bounds__(kBlock) void k_group_table(int32_t* __restrict__ table,
+                                                        const DevState* __restrict__ st) {
+  if (st->done) return;
+  const int beta = st->beta;
+  const uint64_t cells = static_cast<uint64_t>(beta) * beta;
+  const Bijection f(cells, st->keys);
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kBlock;
+  for (uint64_t t = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; t < cells; t += stride) {
+    const uint32_t v = static_cast<uint32_t>(f(t));
+    const uint32_t ly = v / static_cast<uint32_t>(beta);
+    const uint32_t lx = v - ly * static_cast<uint32_t>(beta);
+    table[t] = static_cast<int32_t>((ly << 16) | lx);
+  }
+}
+
+// ------------------------------------------------------------- assignment
+
+// Squared distance partial over one lane's 4 channels, as the two lowest
+// levels of the pairwise tree: (c0^2 + c1^2) + (c2^2 + c3^2).
+__device__ inline float chunk_sq(const float4 a, const float4 b) {
+  const float e0 = a.x - b.x, e1 = a.y - b.y, e2 = a.z - b.z, e3 = a.w - b.w;
+  return (e0 * e0 + e1 * e1) + (e2 * e2 + e3 * e3);
+}
+
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+// Position code of an ordering: sigma(i) in bits 2i..2i+1.
+#define PLAS_CODE(a, b, c, e) ((a) | ((b) << 2) | ((c) << 4) | ((e) << 6))
+#define PLAS_TRY(a, b, c, e)                                                  \
+  {                                                                           \
+    const unsigned long long cost_ = q[0][a] + q[1][b] + q[2][c] + q[3][e];   \
+    if (cost_ < best) {                                                       \
+      best = cost_;                                                           \
+      code = PLAS_CODE(a, b, c, e);                                           \
+    }                                                                         \
+  }
+
+// One reorder's blockwise assignment. Items are the groups of every block
+// (item < groups) followed by the cells in no group (singles), whose
+// distance still counts towards the energy. LG = DP/4 lanes serve one item:
+// lane `sub` holds channels 4*sub .. 4*sub+3 of the item's four grid cells
+// and four target cells and forms all 16 pair partials; xor-butterflies over
+// the LG lanes complete the pairwise channel tree (level by level, left half
+// plus right half), so every lane ends with the 16 exact distances.
+template <int DP>
+__global__ __launch_bounds__(kBlock) void k_assign(float* __restrict__ G, const float* __restrict__ T,
+                                                   int32_t* __restrict__ P,
+                                                   const int32_t* __restrict__ table,
+                                                   DevState* __restrict__ st) {
+  if (st->done) return;
+  constexpr int LG = DP / 4;
+  constexpr int IPW = 64 / LG;
+  const int w = st->w, beta = st->beta, nb = st->nb, dy = st->dy, dx = st->dx;
+  const int64_t gpb = st->groups_per_block;
+  const int64_t groups = st->groups;
+  const int64_t total = groups + st->singles;
+  const double scale = ldexp(1.0, st->s);
+  const int lane = threadIdx.x & 63;
+  const int sub = lane % LG, slot = lane / LG;
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * kBlock) >> 6;
+  const int R = nb * beta;
+  const int64_t strip_rows = static_cast<int64_t>(w - R) * w;
+  const int64_t strip = static_cast<int64_t>(w) * w - static_cast<int64_t>(R) * R;
+  const float4* __restrict__ G4 = reinterpret_cast<const float4*>(G);
+  const float4* __restrict__ T4 = reinterpret_cast<const float4*>(T);
+  float4* __restrict__ Gout = reinterpret_cast<float4*>(G);
+  unsigned long long e_acc = 0, m_acc = 0;
+
+  for (int64_t first = wave * IPW; first < total; first += nwaves * IPW) {
+    const int64_t item = first + slot;
+    const bool active = item < total;
+    const bool is_group = item < groups;
+    int64_t cell[4];
+    if (is_group) {
+      const int64_t b = item / gpb;
+      const int64_t g = item - b * gpb;
+      const int by = static_cast<int>(b / nb);
+      const int bx = static_cast<int>(b - static_cast<int64_t>(by) * nb);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int32_t t = table[4 * g + i];
+        int y = dy + by * beta + (t >> 16);
+        int x = dx + bx * beta + (t & 0xffff);
+        if (y >= w) y -= w;
+        if (x >= w) x -= w;
+        cell[i] = static_cast<int64_t>(y) * w + x;
+      }
+    } else {
+      int64_t p = 0;
+      if (active) {
+        const int64_t t = item - groups;
+        int u, v;
+        if (t < strip) {
+          // Rolled-grid cells outside the nb*beta square: first the full
+          // rows below it, then the columns right of it.
+          if (t < strip_rows) {
+            u = R + static_cast<int>(t / w);
+            v = static_cast<int>(t % w);
+          } else {
+            const int64_t t2 = t - strip_rows;
+            u = static_cast<int>(t2 / (w - R));
+            v = R + static_cast<int>(t2 % (w - R));
+          }
+        } else {
+          // The left-over cell pi(beta^2 - 1) of each block (odd beta).
+          const int64_t b = t - strip;
+          const int by = static_cast<int>(b / nb);
+          const int bx = static_cast<int>(b - static_cast<int64_t>(by) * nb);
+          const int32_t tt = table[static_cast<int64_t>(beta) * beta - 1];
+          u = by * beta + (tt >> 16);
+          v = bx * beta + (tt & 0xffff);
+        }
+        int y = u + dy, x = v + dx;
+        if (y >= w) y -= w;
+        if (x >= w) x -= w;
+        p = static_cast<int64_t>(y) * w + x;
+      }
+      cell[0] = cell[1] = cell[2] = cell[3] = p;
+    }
+
+    float4 g[4], tg[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      g[i] = G4[cell[i] * LG + sub];
+      tg[i] = T4[cell[i] * LG + sub];
+    }
+    float d[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) d[i][j] = chunk_sq(g[i], tg[j]);
+#pragma unroll
+    for (int m = 1; m < LG; m <<= 1)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) d[i][j] = d[i][j] + __shfl_xor(d[i][j], m);
+
+    unsigned long long q[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        q[i][j] = static_cast<unsigned long long>(static_cast<double>(d[i][j]) * scale);
+
+    // First minimum over the 24 orderings in lexicographic order.
+    unsigned long long best = q[0][0] + q[1][1] + q[2][2] + q[3][3];
+    uint32_t code = PLAS_CODE(0, 1, 2, 3);
+    PLAS_TRY(0, 1, 3, 2) PLAS_TRY(0, 2, 1, 3) PLAS_TRY(0, 2, 3, 1) PLAS_TRY(0, 3, 1, 2)
+    PLAS_TRY(0, 3, 2, 1) PLAS_TRY(1, 0, 2, 3) PLAS_TRY(1, 0, 3, 2) PLAS_TRY(1, 2, 0, 3)
+    PLAS_TRY(1, 2, 3, 0) PLAS_TRY(1, 3, 0, 2) PLAS_TRY(1, 3, 2, 0) PLAS_TRY(2, 0, 1, 3)
+    PLAS_TRY(2, 0, 3, 1) PLAS_TRY(2, 1, 0, 3) PLAS_TRY(2, 1, 3, 0) PLAS_TRY(2, 3, 0, 1)
+    PLAS_TRY(2, 3, 1, 0) PLAS_TRY(3, 0, 1, 2) PLAS_TRY(3, 0, 2, 1) PLAS_TRY(3, 1, 0, 2)
+    PLAS_TRY(3, 1, 2, 0) PLAS_TRY(3, 2, 0, 1) PLAS_TRY(3, 2, 1, 0)
+
+    if (is_group && code != PLAS_CODE(0, 1, 2, 3)) {
+      int32_t old_perm[4];
+      if (sub == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) old_perm[i] = P[cell[i]];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int to = (code >> (2 * i)) & 3;
+        if (to != i) {
+          const int64_t dst = to == 0 ? cell[0] : to == 1 ? cell[1] : to == 2 ? cell[2] : cell[3];
+          Gout[dst * LG + sub] = g[i];
+          if (sub == 0) {
+            P[dst] = old_perm[i];
+            ++m_acc;
+          }
+        }
+      }
+    }
+    if (active && sub == 0) e_acc += is_group ? best : q[0][0];
+  }
+  e_acc = wave_sum_u64(e_acc);
+  m_acc = wave_sum_u64(m_acc);
+  if (lane == 0) {
+    const int slot_acc = static_cast<int>(wave % kAccSlots);
+    atomicAdd(&st->energy_acc[slot_acc], e_acc);
+    atomicAdd(&st->moved_acc[slot_acc], m_acc);
+  }
+}
+
+#undef PLAS_TRY
+#undef PLAS_CODE
+
+// ----------------------------------------------------------------- energy
+
+template <int DP>
+__global__ __launch_bounds__(kBlock) void k_energy(const float* __restrict__ G, const float* __restrict__ T,
+                                                   int64_t n, double scale,
+                                                   unsigned long long* __restrict__ out) {
+  constexpr int LG = DP / 4;
+  constexpr int IPW = 64 / LG;
+  const int lane = threadIdx.x & 63;
+  const int sub = lane % LG, slot = lane / LG;
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * kBlock) >> 6;
+  const float4* __restrict__ G4 = reinterpret_cast<const float4*>(G);
+  const float4* __restrict__ T4 = reinterpret_cast<const float4*>(T);
+  unsigned long long acc = 0;
+  for (int64_t first = wave * IPW; first < n; first += nwaves * IPW) {
+    const int64_t p = first + slot;
+    const int64_t pc = p < n ? p : 0;
+    float v = chunk_sq(G4[pc * LG + sub], T4[pc * LG + sub]);
+#pragma unroll
+    for (int m = 1; m < LG; m <<= 1) v = v + __shfl_xor(v, m);
+    if (p < n && sub == 0) acc += static_cast<unsigned long long>(static_cast<double>(v) * scale);
+  }
+  acc = wave_sum_u64(acc);
+  if (lane == 0) atomicAdd(out, acc);
+}
+
+// -------------------------------------------------------------- controller
+
+// Runs once after each reorder (Sec. 3.1): E is compared with the previous
+// energy; an improvement of at least ceil(E_prev / M) keeps the level and
+// its block shift; the first stall draws a new shift; a stall right after a
+// new shift ends the level (phi <- decay * phi, precomputed in `levels`).
+__global__ void k_control(DevState* __restrict__ st, const LevelInfo* __restrict__ levels,
+                          plas_level_out* __restrict__ trace) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (st->done) return;
+  unsigned long long E = 0, moved = 0;
+  for (int i = 0; i < kAccSlots; ++i) {
+    E += st->energy_acc[i];
+    moved += st->moved_acc[i];
+    st->energy_acc[i] = 0;
+    st->moved_acc[i] = 0;
+  }
+  st->k += 1;
+  st->level_reorders += 1;
+  st->level_moved += moved;
+  st->energy_last = E;
+  if (st->level_reorders == 1) st->levels_run += 1;
+  const int L = st->level;
+  plas_level_out& tr = trace[L];
+  tr.phi = levels[L].phi;
+  tr.r = levels[L].r;
+  tr.beta = levels[L].beta;
+  tr.reorders = st->level_reorders;
+  tr.energy_fixed = E;
+  tr.moved = st->level_moved;
+
+  const uint64_t M = st->inv_threshold;
+  const uint64_t prev = st->energy_prev;
+  const bool improved = !st->has_prev || (E < prev && prev - E >= (prev + M - 1) / M);
+  if (improved) {
+    st->energy_prev = E;
+    st->has_prev = 1;
+    st->just_shifted = 0;
+  } else if (st->just_shifted) {
+    const int next = L + 1;
+    if (next >= st->nlevels) {
+      st->done = 1;
+    } else {
+      const LevelInfo lv = levels[next];
+      st->level = next;
+      st->r = lv.r;
+      st->beta = lv.beta;
+      st->nb = lv.nb;
+      st->groups_per_block = lv.groups_per_block;
+      st->groups = lv.groups;
+      st->singles = lv.singles;
+      block_shift(st->seed, st->j, st->w, &st->dy, &st->dx);
+      st->j += 1;
+      st->has_prev = 0;
+      st->just_shifted = 0;
+      st->level_reorders = 0;
+      st->level_moved = 0;
+    }
+  } else {
+    block_shift(st->seed, st->j, st->w, &st->dy, &st->dx);
+    st->j += 1;
+    st->just_shifted = 1;
+    st->energy_prev = E;
+  }
+  if (st->max_reorders > 0 && st->k >= st->max_reorders) st->done = 1;
+  if (!st->done) {
+    const Words4 keys = draw(st->seed, kDrawGrouping, static_cast<uint64_t>(st->k));
+    for (int i = 0; i < 4; ++i) st->keys[i] = keys.v[i];
+  }
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- launchers
+
+#define PLAS_DISPATCH_DP(dp, CALL) \
+  switch (dp) {                    \
+    case 4: { constexpr int DPV = 4; CALL; } break;   \
+    case 8: { constexpr int DPV = 8; CALL; } break;   \
+    case 16: { constexpr int DPV = 16; CALL; } break; \
+    case 32: { constexpr int DPV = 32; CALL; } break; \
+    case 64: { constexpr int DPV = 64; CALL; } break; \
+    default: return hipErrorInvalidValue;             \
+  }
+
+hipError_t launch_ingest(const float* features, int64_t n, int d, int layout, int dp, float* X,
+                         hipStream_t stream) {
+  if (layout == 0) {
+    const int blocks = static_cast<int>((n + 63) / 64);
+    PLAS_DISPATCH_DP(dp, (k_ingest_cn<DPV><<<blocks, kBlock, 0, stream>>>(features, n, d, X)));
+  } else {
+    const int blocks = blocks_for(n * dp, 65536);
+    PLAS_DISPATCH_DP(dp, (k_ingest_nc<DPV><<<blocks, kBlock, 0, stream>>>(features, n, d, X)));
+  }
+  return hipGetLastError();
+}
+
+size_t range_partial_floats(int dp) { return static_cast<size_t>(kRangeBlocks) * 3 * dp; }
+
+hipError_t launch_range(const float* X, int64_t n, int d, int dp, float* part, float* out,
+                        hipStream_t stream) {
+  PLAS_DISPATCH_DP(dp, (k_range_partial<DPV><<<kRangeBlocks, kBlock, 0, stream>>>(X, n, part)));
+  PLAS_DISPATCH_DP(dp, (k_range_finish<DPV><<<1, 64, 0, stream>>>(part, kRangeBlocks, d, out)));
+  return hipGetLastError();
+}
+
+hipError_t launch_start_perm(int32_t* P, int64_t n, const uint64_t keys[4], hipStream_t stream) {
+  Words4 k;
+  for (int i = 0; i < 4; ++i) k.v[i] = keys[i];
+  k_start_perm<<<blocks_for(n), kBlock, 0, stream>>>(P, n, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_perm(const int32_t* init, int64_t n, int32_t* counts, int32_t* flag,
+                             hipStream_t stream) {
+  k_count_perm<<<blocks_for(n), kBlock, 0, stream>>>(init, n, counts, flag);
+  k_verify_counts<<<blocks_for(n), kBlock, 0, stream>>>(counts, n, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const float* X, const int32_t* P, float* G, int64_t n, int dp,
+                         hipStream_t stream) {
+  const int blocks = blocks_for(n * (dp / 4), 65536);
+  PLAS_DISPATCH_DP(dp, (k_gather<DPV><<<blocks, kBlock, 0, stream>>>(X, P, G, n)));
+  return hipGetLastError();
+}
+
+hipError_t launch_blur_pass(const float* in, float* out, int w, int dp, const DevState* st,
+                            int radius, int vertical, const float* inv, hipStream_t stream) {
+  const int lines_per_wave = 64 / dp;
+  const int64_t waves = (w + lines_per_wave - 1) / lines_per_wave;
+  const int blocks = static_cast<int>((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+  PLAS_DISPATCH_DP(dp, (k_blur<DPV><<<blocks, kBlock, 0, stream>>>(in, out, w, st, radius,
+                                                                    vertical, inv)));
+  return hipGetLastError();
+}
+
+hipError_t launch_group_table(int32_t* table, const DevState* st, int64_t max_cells,
+                              hipStream_t stream) {
+  k_group_table<<<blocks_for(max_cells), kBlock, 0, stream>>>(table, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_assign(float* G, const float* T, int32_t* P, const int32_t* table,
+                         DevState* st, int dp, int64_t max_items, hipStream_t stream) {
+  const int64_t items_per_wave = 64 / (dp / 4);
+  const int64_t waves = (max_items + items_per_wave - 1) / items_per_wave;
+  const int blocks = blocks_for(waves * 64);
+  PLAS_DISPATCH_DP(dp, (k_assign<DPV><<<blocks, kBlock, 0, stream>>>(G, T, P, table, st)));
+  return hipGetLastError();
+}
+
+hipError_t launch_control(DevState* st, const LevelInfo* levels, plas_level_out* trace,
+                          hipStream_t stream) {
+  k_control<<<1, 64, 0, stream>>>(st, levels, trace);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(const float* G, const float* T, int64_t n, int dp, int s,
+                         unsigned long long* energy_out, hipStream_t stream) {
+  const int64_t items_per_wave = 64 / (dp / 4);
+  const int64_t waves = (n + items_per_wave - 1) / items_per_wave;
+  const int blocks = blocks_for(waves * 64);
+  const double scale = ldexp(1.0, s);
+  PLAS_DISPATCH_DP(dp, (k_energy<DPV><<<blocks, kBlock, 0, stream>>>(G, T, n, scale, energy_out)));
+  return hipGetLastError();
+}
+
+#undef PLAS_DISPATCH_DP
+
+}  // namespace plas

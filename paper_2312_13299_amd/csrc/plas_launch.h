@@ -1,0 +1,60 @@
+// plas_launch.h -- host-side launchers of the PLAS kernels (plas_kernels.hip).
+// Each enqueues work on `stream` and returns the launch status; none
+// synchronises. `dp` is the padded channel stride of the working layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "plas_device.h"
+
+namespace plas {
+
+struct plas_level_out {  // same layout as plas_level_stat in plas.h
+  double phi;
+  int32_t r;
+  int32_t beta;
+  int64_t reorders;
+  uint64_t energy_fixed;
+  uint64_t moved;
+};
+
+// features (layout CN [d][n] or NC [n][d]) -> X [n][dp], channels >= d zero.
+hipError_t launch_ingest(const float* features, int64_t n, int d, int layout, int dp, float* X,
+                         hipStream_t stream);
+// Per-channel min/max of X[n][dp] over the first d channels, and a flag set
+// if any value is NaN or infinite. out: [dp] mins, [dp] maxs, then the flag
+// (as a float slot holding 0 or 1). part: scratch of range_partials_floats().
+size_t range_partial_floats(int dp);
+hipError_t launch_range(const float* X, int64_t n, int d, int dp, float* part, float* out,
+                        hipStream_t stream);
+// P[p] = bijection(n, keys)(p).
+hipError_t launch_start_perm(int32_t* P, int64_t n, const uint64_t keys[4], hipStream_t stream);
+// Check that init (int32[n]) is a bijection of [0, n): counts is scratch
+// int32[n], flag (device int32) is set to 1 when it is not. counts and flag
+// must be zeroed beforehand.
+hipError_t launch_check_perm(const int32_t* init, int64_t n, int32_t* counts, int32_t* flag,
+                             hipStream_t stream);
+// G[p] = X[P[p]] over dp channels.
+hipError_t launch_gather(const float* X, const int32_t* P, float* G, int64_t n, int dp,
+                         hipStream_t stream);
+// One blur pass (vertical = 0: rows, 1: columns) with the radius of st->r,
+// or `radius` if st is NULL. inv: float32 1/c for c = 0..w.
+hipError_t launch_blur_pass(const float* in, float* out, int w, int dp, const DevState* st,
+                            int radius, int vertical, const float* inv, hipStream_t stream);
+// Grouping table of the current reorder: table[t] = packed pi(t), t < beta^2.
+hipError_t launch_group_table(int32_t* table, const DevState* st, int64_t max_cells,
+                              hipStream_t stream);
+// One blockwise assignment with the parameters in st. max_items bounds
+// groups + singles over every level this launch may see.
+hipError_t launch_assign(float* G, const float* T, int32_t* P, const int32_t* table,
+                         DevState* st, int dp, int64_t max_items, hipStream_t stream);
+// Controller: reads the reorder's energy, applies the stall test, advances
+// the schedule and prepares the next reorder's parameters.
+hipError_t launch_control(DevState* st, const LevelInfo* levels, plas_level_out* trace,
+                          hipStream_t stream);
+// energy_out (device u64) += sum over cells of floor(d(G[p], T[p]) * 2^s).
+hipError_t launch_energy(const float* G, const float* T, int64_t n, int dp, int s,
+                         unsigned long long* energy_out, hipStream_t stream);
+
+}  // namespace plas

@@ -1,0 +1,195 @@
+"""GPU parity of whole sorts against the CPU oracle through plas_sort and
+plas_grid_energy: the permutation, the reorder count, the per-level trace
+and the final integer energy must be equal. The full 1024 x 1024 sort is
+compared with the oracle's stored result (tests/golden, written by
+make_golden.py from the oracle alone)."""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synthetic
+from gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def env(ref):
+    torch, plas = require_gpu()
+    return torch, plas, plas.Context(0), ref
+
+
+def _compare(res_gpu, perm_gpu, res_ref):
+    assert res_gpu.reorders == res_ref.reorders
+    assert res_gpu.levels == res_ref.levels
+    assert res_gpu.energy_fixed == res_ref.energy
+    assert res_gpu.scale_shift == res_ref.scale_shift
+    assert len(res_gpu.trace) == len(res_ref.trace)
+    for a, b in zip(res_gpu.trace, res_ref.trace):
+        assert a["phi"] == b["phi"] and a["r"] == b["r"] and a["beta"] == b["beta"]
+        assert a["reorders"] == b["reorders"] and a["energy"] == b["energy"] and a["moved"] == b["moved"]
+    assert np.array_equal(perm_gpu, res_ref.perm)
+
+
+SMALL = [
+    # (side, d, layout, seed)
+    (2, 3, "cn", 1), (3, 3, "cn", 2), (4, 1, "nc", 3), (5, 2, "cn", 4), (8, 59, "cn", 5),
+    (16, 3, "nc", 6), (17, 14, "cn", 7), (31, 59, "nc", 8), (33, 64, "cn", 9), (48, 8, "cn", 10),
+]
+
+
+@pytest.mark.parametrize("side,d,layout,seed", SMALL)
+def test_small_sorts_match_oracle(env, side, d, layout, seed):
+    torch, plas, ctx, ref = env
+    N = side * side
+    F = synthetic.random_features(N, d, seed, layout, -2.0, 2.0) if d != 59 else \
+        synthetic.gaussian_attributes(N, seed, layout)
+    perm, res = ctx.sort(torch.from_numpy(F).cuda(), side, seed, layout)
+    want = ref.sort(F, side, seed, layout)
+    assert want.status == 0
+    _compare(res, perm.cpu().numpy(), want)
+
+
+def test_scene_64_d59_matches_oracle(env):
+    """The 64 x 64, D = 59 workload: full sort, bit-exact."""
+    torch, plas, ctx, ref = env
+    F = synthetic.gaussian_attributes(64 * 64, synthetic.DATA_SEED_SMALL)
+    perm, res = ctx.sort(torch.from_numpy(F).cuda(), 64, synthetic.SORT_SEED)
+    want = ref.sort(F, 64, synthetic.SORT_SEED)
+    _compare(res, perm.cpu().numpy(), want)
+    assert res.levels == 67
+
+
+@pytest.mark.parametrize("start_radius,max_reorders", [(0.0, 3), (0.0, 7), (2.5, 6), (1.0, 5)])
+def test_scene_1024_truncated_matches_oracle(env, start_radius, max_reorders):
+    """1024 x 1024, D = 59: the first reorders of the coarsest levels and of
+    the finest levels, bit-exact."""
+    torch, plas, ctx, ref = env
+    side = 1024
+    F = synthetic.gaussian_attributes(side * side, synthetic.DATA_SEED_SCENE)
+    perm, res = ctx.sort(torch.from_numpy(F).cuda(), side, synthetic.SORT_SEED,
+                         start_radius=start_radius, max_reorders=max_reorders)
+    want = ref.sort(F, side, synthetic.SORT_SEED, start_radius=start_radius, max_reorders=max_reorders)
+    _compare(res, perm.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("name", ["sort_256_d59", "sort_1024_d59"])
+def test_full_sort_matches_stored_oracle_result(env, name):
+    torch, plas, ctx, ref = env
+    path = os.path.join(GOLDEN, f"{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    gold = json.load(open(path))
+    side = gold["side"]
+    F = synthetic.gaussian_attributes(side * side, gold["data_seed"])
+    perm, res = ctx.sort(torch.from_numpy(F).cuda(), side, gold["sort_seed"])
+    p = perm.cpu().numpy().astype("<i4")
+    assert res.reorders == gold["reorders"]
+    assert res.levels == gold["levels"]
+    assert res.energy_fixed == int(gold["energy"])
+    assert [t["reorders"] for t in res.trace] == [t["reorders"] for t in gold["trace"]]
+    assert [t["energy"] for t in res.trace] == [int(t["energy"]) for t in gold["trace"]]
+    assert list(p[:16]) == gold["perm_head"]
+    assert hashlib.sha256(p.tobytes()).hexdigest() == gold["perm_sha256"]
+
+
+def test_result_is_a_valid_arrangement(env):
+    torch, plas, ctx, ref = env
+    side = 40
+    F = synthetic.gaussian_attributes(side * side, 12)
+    perm, res = ctx.sort(torch.from_numpy(F).cuda(), side, 3)
+    p = perm.cpu().numpy()
+    assert np.array_equal(np.sort(p), np.arange(side * side))
+    assert ref.grid_energy_f64(F, p, side, 1) < 0.6 * ref.grid_energy_f64(F, None, side, 1)
+
+
+def test_init_perm_and_repeatability(env):
+    torch, plas, ctx, ref = env
+    side = 24
+    F = synthetic.gaussian_attributes(side * side, 13)
+    init = synthetic.random_permutation(side * side, 5)
+    f_dev = torch.from_numpy(F).cuda()
+    perm, res = ctx.sort(f_dev, side, 9, init_perm=torch.from_numpy(init).cuda())
+    want = ref.sort(F, side, 9, init_perm=init)
+    _compare(res, perm.cpu().numpy(), want)
+    perm2, _ = ctx.sort(f_dev, side, 9, init_perm=torch.from_numpy(init).cuda())
+    assert torch.equal(perm, perm2)
+
+
+def test_constant_features(env):
+    torch, plas, ctx, ref = env
+    side = 20
+    F = np.full((3, side * side), 0.25, dtype=np.float32)
+    perm, res = ctx.sort(torch.from_numpy(F).cuda(), side, 1)
+    want = ref.sort(F, side, 1)
+    _compare(res, perm.cpu().numpy(), want)
+    assert all(t["reorders"] == 3 for t in res.trace) and res.energy_fixed == 0
+
+
+def test_chunking_does_not_change_the_result(env):
+    torch, plas, ctx, ref = env
+    side = 32
+    F = torch.from_numpy(synthetic.gaussian_attributes(side * side, 14)).cuda()
+    a, ra = ctx.sort(F, side, 4, reorders_per_sync=1)
+    b, rb = ctx.sort(F, side, 4, reorders_per_sync=97)
+    c, rc = ctx.sort(F, side, 4, profile=True)
+    assert torch.equal(a, b) and torch.equal(a, c)
+    assert ra.reorders == rb.reorders == rc.reorders
+    assert rc.assign_launches == rc.reorders and rc.blur_launches == 2 * rc.reorders
+    assert rc.assign_ms > 0 and rc.blur_ms > 0
+
+
+@pytest.mark.parametrize("side,d,r,layout", [(16, 59, 1, "cn"), (33, 3, 4, "nc"), (64, 59, 0, "cn"),
+                                             (100, 14, 9, "cn")])
+def test_grid_energy_matches_oracle(env, side, d, r, layout):
+    torch, plas, ctx, ref = env
+    N = side * side
+    F = synthetic.random_features(N, d, side, layout, -3, 3)
+    perm = synthetic.random_permutation(N, side)
+    f_dev = torch.from_numpy(F).cuda()
+    E, s, mean = ctx.grid_energy(f_dev, torch.from_numpy(perm).cuda(), side, r, layout)
+    st, E_ref, s_ref, mean_ref = ref.grid_energy(F, perm, side, r, layout)
+    assert (E, s) == (E_ref, s_ref) and mean == mean_ref
+    E0, _, _ = ctx.grid_energy(f_dev, None, side, r, layout)
+    assert E0 == ref.grid_energy(F, None, side, r, layout)[1]
+
+
+def test_errors_are_reported(env):
+    torch, plas, ctx, ref = env
+    F = torch.from_numpy(synthetic.gaussian_attributes(64, 1)).cuda()
+    with pytest.raises(plas.PlasError) as e:
+        ctx.sort(F, 7)
+    assert e.value.status == plas.ERR_INVALID_ARGUMENT
+    bad = F.clone()
+    bad[5, 3] = float("nan")
+    with pytest.raises(plas.PlasError) as e:
+        ctx.sort(bad, 8)
+    assert e.value.status == plas.ERR_NONFINITE
+    bad[5, 3] = float("inf")
+    with pytest.raises(plas.PlasError) as e:
+        ctx.grid_energy(bad, None, 8, 1)
+    assert e.value.status == plas.ERR_NONFINITE
+    wide = torch.zeros((65, 64), dtype=torch.float32, device="cuda")
+    with pytest.raises(plas.PlasError) as e:
+        ctx.sort(wide, 8)
+    assert e.value.status == plas.ERR_UNSUPPORTED
+    init = torch.arange(64, dtype=torch.int32, device="cuda")
+    init[3] = 4
+    with pytest.raises(plas.PlasError) as e:
+        ctx.sort(F, 8, init_perm=init)
+    assert e.value.status == plas.ERR_INVALID_ARGUMENT
+    init[3] = 64
+    with pytest.raises(plas.PlasError) as e:
+        ctx.sort(F, 8, init_perm=init)
+    assert e.value.status == plas.ERR_INVALID_ARGUMENT
+    with pytest.raises(plas.PlasError) as e:
+        ctx.sort(F, 8, radius_decay=1.5)
+    assert e.value.status == plas.ERR_INVALID_ARGUMENT
+    # The handle still works after errors.
+    perm, res = ctx.sort(F, 8, 3)
+    assert res.reorders > 0
