@@ -41,6 +41,10 @@
 #include <string.h>
 #include <omp.h>
 
+/* Loops over fewer items than this run on one thread: the work is too small
+ * to repay starting a parallel region. Thread count never changes results. */
+#define PAR_MIN_ITEMS 16384
+
 /* ------------------------------------------------------------------------ */
 /* Random numbers: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel      */
 /* Random Numbers: As Easy as 1, 2, 3", SC'11). The paper only says          */
@@ -154,7 +158,7 @@ uint64_t plas_ref_bijection(uint64_t n, const uint64_t rk[4], uint64_t i)
 
 void plas_ref_bijection_table(uint64_t n, const uint64_t rk[4], int64_t* out)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= PAR_MIN_ITEMS)
     for (int64_t i = 0; i < (int64_t)n; i++)
         out[i] = (int64_t)plas_ref_bijection(n, rk, (uint64_t)i);
 }
@@ -291,12 +295,12 @@ int32_t plas_ref_blur(const float* G, float* T, int32_t w, int32_t d, int32_t r)
     for (int32_t c = 1; c <= w; c++)
         inv[c] = 1.0f / (float)c;
     /* Horizontal pass: every row, every channel. */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= PAR_MIN_ITEMS)
     for (int32_t y = 0; y < w; y++)
         for (int32_t c = 0; c < d; c++)
             box_line(G + (int64_t)y * w * d + c, d, H + (int64_t)y * w * d + c, w, r, inv);
     /* Vertical pass on the result: every column, every channel. */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= PAR_MIN_ITEMS)
     for (int32_t x = 0; x < w; x++)
         for (int32_t c = 0; c < d; c++)
             box_line(H + (int64_t)x * d + c, (ptrdiff_t)w * d, T + (int64_t)x * d + c, w, r, inv);
@@ -354,7 +358,7 @@ uint64_t plas_ref_quantise(float dist, int32_t s)
 uint64_t plas_ref_energy_fixed(const float* G, const float* T, int64_t N, int32_t d, int32_t s)
 {
     uint64_t E = 0;
-#pragma omp parallel for schedule(static) reduction(+ : E)
+#pragma omp parallel for schedule(static) reduction(+ : E) if (N >= PAR_MIN_ITEMS)
     for (int64_t p = 0; p < N; p++)
         E += plas_ref_quantise(plas_ref_distance(G + p * d, T + p * d, d), s);
     return E;
@@ -417,55 +421,54 @@ uint64_t plas_ref_assign(float* G, const float* T, int32_t* P, int32_t w, int32_
     plas_ref_bijection_table((uint64_t)cells_per_block, rk, pi);
 
     uint64_t E = 0, moved = 0;
-#pragma omp parallel for schedule(static) reduction(+ : E, moved)
-    for (int64_t blk = 0; blk < (int64_t)nb * nb; blk++) {
+    const int64_t total_groups = (int64_t)nb * nb * groups_per_block;
+#pragma omp parallel for schedule(static) reduction(+ : E, moved) if (N >= PAR_MIN_ITEMS)
+    for (int64_t item = 0; item < total_groups; item++) {
+        int64_t blk = item / groups_per_block, g = item % groups_per_block;
         int64_t by = blk / nb, bx = blk % nb;
-        float* saved = (float*)malloc(sizeof(float) * (size_t)(4 * d));
-        for (int64_t g = 0; g < groups_per_block; g++) {
-            int64_t cell[4];
-            for (int i = 0; i < 4; i++) {
-                int64_t local = pi[4 * g + i];
-                int64_t ly = local / beta, lx = local % beta;
-                int64_t y = (dy + by * beta + ly) % w;
-                int64_t x = (dx + bx * beta + lx) % w;
-                cell[i] = y * w + x;
-            }
-            uint64_t q[4][4];
-            for (int i = 0; i < 4; i++)
-                for (int j = 0; j < 4; j++)
-                    q[i][j] = plas_ref_quantise(
-                        plas_ref_distance(G + cell[i] * d, T + cell[j] * d, d), s);
-            int best = 0;
-            uint64_t best_cost = 0;
-            for (int m = 0; m < 24; m++) {
-                const int32_t* sg = perms + 4 * m;
-                uint64_t cost = q[0][sg[0]] + q[1][sg[1]] + q[2][sg[2]] + q[3][sg[3]];
-                if (m == 0 || cost < best_cost) {
-                    best = m;
-                    best_cost = cost;
-                }
-            }
-            E += best_cost;
-            const int32_t* sg = perms + 4 * best;
-            int32_t saved_perm[4];
-            for (int i = 0; i < 4; i++) {
-                memcpy(saved + i * d, G + cell[i] * d, sizeof(float) * (size_t)d);
-                saved_perm[i] = P[cell[i]];
-            }
-            for (int i = 0; i < 4; i++) {
-                int64_t dst = cell[sg[i]];
-                memcpy(G + dst * d, saved + i * d, sizeof(float) * (size_t)d);
-                P[dst] = saved_perm[i];
-                if (sg[i] != i)
-                    moved++;
-                grouped[cell[i]] = 1;
+        int64_t cell[4];
+        for (int i = 0; i < 4; i++) {
+            int64_t local = pi[4 * g + i];
+            int64_t ly = local / beta, lx = local % beta;
+            int64_t y = (dy + by * beta + ly) % w;
+            int64_t x = (dx + bx * beta + lx) % w;
+            cell[i] = y * w + x;
+        }
+        uint64_t q[4][4];
+        for (int i = 0; i < 4; i++)
+            for (int j = 0; j < 4; j++)
+                q[i][j] = plas_ref_quantise(
+                    plas_ref_distance(G + cell[i] * d, T + cell[j] * d, d), s);
+        int best = 0;
+        uint64_t best_cost = 0;
+        for (int m = 0; m < 24; m++) {
+            const int32_t* sg = perms + 4 * m;
+            uint64_t cost = q[0][sg[0]] + q[1][sg[1]] + q[2][sg[2]] + q[3][sg[3]];
+            if (m == 0 || cost < best_cost) {
+                best = m;
+                best_cost = cost;
             }
         }
-        free(saved);
+        E += best_cost;
+        const int32_t* sg = perms + 4 * best;
+        float saved[4 * PLAS_REF_MAX_D];
+        int32_t saved_perm[4];
+        for (int i = 0; i < 4; i++) {
+            memcpy(saved + i * d, G + cell[i] * d, sizeof(float) * (size_t)d);
+            saved_perm[i] = P[cell[i]];
+        }
+        for (int i = 0; i < 4; i++) {
+            int64_t dst = cell[sg[i]];
+            memcpy(G + dst * d, saved + i * d, sizeof(float) * (size_t)d);
+            P[dst] = saved_perm[i];
+            if (sg[i] != i)
+                moved++;
+            grouped[cell[i]] = 1;
+        }
     }
     /* Cells that were in no group keep their place; their distance still
      * counts, because the energy covers the whole grid. */
-#pragma omp parallel for schedule(static) reduction(+ : E)
+#pragma omp parallel for schedule(static) reduction(+ : E) if (N >= PAR_MIN_ITEMS)
     for (int64_t p = 0; p < N; p++)
         if (!grouped[p])
             E += plas_ref_quantise(plas_ref_distance(G + p * d, T + p * d, d), s);
@@ -729,7 +732,7 @@ double plas_ref_grid_energy_f64(const float* F, const int32_t* perm, int64_t n, 
         for (int32_t c = 0; c < d; c++)
             G[p * d + c] = (double)feature_at(F, n, d, layout, src, c);
     }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= PAR_MIN_ITEMS)
     for (int32_t y = 0; y < w; y++)
         for (int32_t x = 0; x < w; x++) {
             int32_t lo = x - r < 0 ? 0 : x - r, hi = x + r > w - 1 ? w - 1 : x + r;
@@ -740,7 +743,7 @@ double plas_ref_grid_energy_f64(const float* F, const int32_t* perm, int64_t n, 
                 H[((int64_t)y * w + x) * d + c] = acc / (double)(hi - lo + 1);
             }
         }
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= PAR_MIN_ITEMS)
     for (int32_t y = 0; y < w; y++)
         for (int32_t x = 0; x < w; x++) {
             int32_t lo = y - r < 0 ? 0 : y - r, hi = y + r > w - 1 ? w - 1 : y + r;
