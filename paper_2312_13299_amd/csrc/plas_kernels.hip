@@ -13,6 +13,8 @@
 // equal, bit for bit, to a CPU that evaluates the same expressions.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "plas_launch.h"
 #include "plas_random.h"
 
@@ -186,6 +188,79 @@ __global__ __launch_bounds__(kBlock) void k_gather(const float* __restrict__ X, 
 // min(r, w-1) + 1 values; at each next position the entering value is added
 // and then the leaving value subtracted, and the output is the running sum
 // times float32(1 / count) for the window clipped to the grid.
+//
+// The running sum is a serial chain per (line, channel), so a wave cannot
+// hide memory latency by switching lines. Instead each lane keeps the loads
+// of the next kBlurUnroll positions in flight while it adds up the current
+// ones (two register buffers used in turn). The line is cut into ranges where
+// "a value enters" and "a value leaves" are fixed, which keeps the unrolled
+// loops free of per-position tests; the position x is the same for all lanes
+// of a wave, so every remaining branch is uniform.
+constexpr int kBlurUnroll = 12;
+
+struct BlurLine {
+  const float* __restrict__ src;
+  float* __restrict__ dst;
+  int64_t step;
+  const float* __restrict__ inv;
+  int w;
+  int r;
+
+  __device__ __forceinline__ float load(int t) const { return src[static_cast<int64_t>(t) * step]; }
+  __device__ __forceinline__ void store(int x, float s) const {
+    const int hi = x + r < w - 1 ? x + r : w - 1;
+    const int lo = x - r > 0 ? x - r : 0;
+    dst[static_cast<int64_t>(x) * step] = s * inv[hi - lo + 1];
+  }
+};
+
+template <bool ENTER, bool LEAVE>
+__device__ __forceinline__ void blur_fetch(const BlurLine& L, int x0, float* enter, float* leave) {
+#pragma unroll
+  for (int i = 0; i < kBlurUnroll; ++i) {
+    if (ENTER) enter[i] = L.load(x0 + i + L.r);
+    if (LEAVE) leave[i] = L.load(x0 + i - L.r - 1);
+  }
+}
+
+template <bool ENTER, bool LEAVE>
+__device__ __forceinline__ void blur_apply(const BlurLine& L, int x0, const float* enter, const float* leave,
+                                           float& s) {
+#pragma unroll
+  for (int i = 0; i < kBlurUnroll; ++i) {
+    if (ENTER) s = s + enter[i];
+    if (LEAVE) s = s - leave[i];
+    L.store(x0 + i, s);
+  }
+}
+
+// Positions [xb, xe) where entering/leaving values exist as ENTER/LEAVE say.
+template <bool ENTER, bool LEAVE>
+__device__ __forceinline__ void blur_range(const BlurLine& L, int xb, int xe, float& s) {
+  const int full = (xe - xb) / kBlurUnroll;
+  int x = xb;
+  if (full > 0) {
+    float ea[kBlurUnroll], la[kBlurUnroll], eb[kBlurUnroll], lb[kBlurUnroll];
+    blur_fetch<ENTER, LEAVE>(L, x, ea, la);
+    int c = 0;
+    for (;;) {
+      if (c + 1 < full) blur_fetch<ENTER, LEAVE>(L, x + kBlurUnroll, eb, lb);
+      blur_apply<ENTER, LEAVE>(L, x, ea, la, s);
+      x += kBlurUnroll;
+      if (++c == full) break;
+      if (c + 1 < full) blur_fetch<ENTER, LEAVE>(L, x + kBlurUnroll, ea, la);
+      blur_apply<ENTER, LEAVE>(L, x, eb, lb, s);
+      x += kBlurUnroll;
+      if (++c == full) break;
+    }
+  }
+  for (; x < xe; ++x) {
+    if (ENTER) s = s + L.load(x + L.r);
+    if (LEAVE) s = s - L.load(x - L.r - 1);
+    L.store(x, s);
+  }
+}
+
 template <int DP>
 __global__ __launch_bounds__(kBlock) void k_blur(const float* __restrict__ in, float* __restrict__ out,
                                                  int w, const DevState* __restrict__ st, int radius,
@@ -199,23 +274,42 @@ __global__ __launch_bounds__(kBlock) void k_blur(const float* __restrict__ in, f
   const int c = lane % DP;
   if (line >= w) return;
   const int64_t base = vertical ? line * DP + c : line * w * DP + c;
-  const int64_t step = vertical ? static_cast<int64_t>(w) * DP : DP;
-  const float* __restrict__ src = in + base;
-  float* __restrict__ dst = out + base;
+  BlurLine L;
+  L.src = in + base;
+  L.dst = out + base;
+  L.step = vertical ? static_cast<int64_t>(w) * DP : DP;
+  L.inv = inv;
+  L.w = w;
+  L.r = r;
   if (r == 0) {
-    for (int x = 0; x < w; ++x) dst[x * step] = src[x * step];
+    for (int x = 0; x < w; ++x) L.dst[x * L.step] = L.src[x * L.step];
     return;
   }
+  // Start: ascending sum of positions 0 .. first_hi, loaded kBlurUnroll at a time.
   const int first_hi = r < w - 1 ? r : w - 1;
-  float s = src[0];
-  for (int t = 1; t <= first_hi; ++t) s = s + src[t * step];
-  dst[0] = s * inv[first_hi + 1];
-  for (int x = 1; x < w; ++x) {
-    if (x + r <= w - 1) s = s + src[static_cast<int64_t>(x + r) * step];
-    if (x - r - 1 >= 0) s = s - src[static_cast<int64_t>(x - r - 1) * step];
-    const int hi = x + r < w - 1 ? x + r : w - 1;
-    const int lo = x - r > 0 ? x - r : 0;
-    dst[x * step] = s * inv[hi - lo + 1];
+  float s = L.load(0);
+  int t = 1;
+  for (; t + kBlurUnroll - 1 <= first_hi; t += kBlurUnroll) {
+    float v[kBlurUnroll];
+#pragma unroll
+    for (int i = 0; i < kBlurUnroll; ++i) v[i] = L.load(t + i);
+#pragma unroll
+    for (int i = 0; i < kBlurUnroll; ++i) s = s + v[i];
+  }
+  for (; t <= first_hi; ++t) s = s + L.load(t);
+  L.store(0, s);
+  // Position x has an entering value iff x + r <= w - 1 and a leaving value
+  // iff x - r - 1 >= 0. Both bounds split [1, w) into at most three ranges.
+  const int enter_end = w - r < 1 ? 1 : (w - r > w ? w : w - r);  // x < enter_end: entering
+  const int leave_begin = r + 1 < w ? r + 1 : w;                 // x >= leave_begin: leaving
+  if (enter_end <= leave_begin) {
+    blur_range<true, false>(L, 1, enter_end, s);
+    blur_range<false, false>(L, enter_end, leave_begin, s);
+    blur_range<false, true>(L, leave_begin, w, s);
+  } else {
+    blur_range<true, false>(L, 1, leave_begin, s);
+    blur_range<true, true>(L, leave_begin, enter_end, s);
+    blur_range<false, true>(L, enter_end, w, s);
   }
 }
 
@@ -416,6 +510,200 @@ __global__ __launch_bounds__(kBlock) void k_assign(float* __restrict__ G, const 
 #undef PLAS_TRY
 #undef PLAS_CODE
 
+// The 24 orderings of (0,1,2,3) in lexicographic order as position codes
+// (sigma(i) in bits 2i..2i+1), eight codes per 64-bit word, ordering m in
+// byte m mod 8 of word m / 8:
+//   0123 0132 0213 0231 0312 0321 1023 1032 | 1203 1230 1302 1320 2013 2031
+//   2103 2130 | 2301 2310 3012 3021 3102 3120 3201 3210
+__device__ __forceinline__ uint32_t order_code(int m) {
+  constexpr uint64_t kOrders0 = 0xB1E16C9C78D8B4E4ull;
+  constexpr uint64_t kOrders1 = 0x36C672D22D8D39C9ull;
+  constexpr uint64_t kOrders2 = 0x1B4B278763931E4Eull;
+  const uint64_t word = m < 8 ? kOrders0 : (m < 16 ? kOrders1 : kOrders2);
+  return static_cast<uint32_t>((word >> (8 * (m & 7))) & 0xff);
+}
+
+// Assignment, second form. Same items and results as k_assign; the work
+// after the distance partials is split across the LG lanes of an item:
+//  - a transposed butterfly: at tree level b each lane keeps the pairs whose
+//    bit b matches its own lane bit, adds the partner's partial for them and
+//    hands over the others, so after log2(LG) levels lane L holds the exact
+//    distances of pairs q = t*LG + L (each still summed left half + right
+//    half, level by level, as the channel tree prescribes);
+//  - the quantised pair costs go to LDS; lane L evaluates orderings
+//    L, L+LG, ... and the lanes pick the first minimum with a butterfly on
+//    (cost, ordering index).
+template <int DP>
+__global__ __launch_bounds__(kBlock) void k_assign2(float* __restrict__ G, const float* __restrict__ T,
+                                                    int32_t* __restrict__ P,
+                                                    const int32_t* __restrict__ table,
+                                                    DevState* __restrict__ st) {
+  if (st->done) return;
+  constexpr int LG = DP / 4;
+  constexpr int IPW = 64 / LG;
+  constexpr int LEVELS = LG == 1 ? 0 : LG == 2 ? 1 : LG == 4 ? 2 : LG == 8 ? 3 : 4;
+  constexpr int KEEP = 16 / LG;  // pair distances held per lane after the reduction
+  __shared__ unsigned long long s_q[kWavesPerBlock][IPW][16];
+  const int w = st->w, beta = st->beta, nb = st->nb, dy = st->dy, dx = st->dx;
+  const int64_t gpb = st->groups_per_block;
+  const int64_t groups = st->groups;
+  const int64_t total = groups + st->singles;
+  const double scale = ldexp(1.0, st->s);
+  const int lane = threadIdx.x & 63;
+  const int wib = threadIdx.x >> 6;
+  const int sub = lane % LG, slot = lane / LG;
+  unsigned long long* q_item = s_q[wib][slot];
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * kBlock) >> 6;
+  const int R = nb * beta;
+  const int64_t strip_rows = static_cast<int64_t>(w - R) * w;
+  const int64_t strip = static_cast<int64_t>(w) * w - static_cast<int64_t>(R) * R;
+  const float4* __restrict__ G4 = reinterpret_cast<const float4*>(G);
+  const float4* __restrict__ T4 = reinterpret_cast<const float4*>(T);
+  float4* __restrict__ Gout = reinterpret_cast<float4*>(G);
+  unsigned long long e_acc = 0, m_acc = 0;
+
+  for (int64_t first = wave * IPW; first < total; first += nwaves * IPW) {
+    const int64_t item = first + slot;
+    const bool active = item < total;
+    const bool is_group = item < groups;
+    int64_t cell[4];
+    if (is_group) {
+      const int64_t b = item / gpb;
+      const int64_t g = item - b * gpb;
+      const int by = static_cast<int>(b / nb);
+      const int bx = static_cast<int>(b - static_cast<int64_t>(by) * nb);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int32_t t = table[4 * g + i];
+        int y = dy + by * beta + (t >> 16);
+        int x = dx + bx * beta + (t & 0xffff);
+        if (y >= w) y -= w;
+        if (x >= w) x -= w;
+        cell[i] = static_cast<int64_t>(y) * w + x;
+      }
+    } else {
+      int64_t p = 0;
+      if (active) {
+        const int64_t t = item - groups;
+        int u, v;
+        if (t < strip) {
+          if (t < strip_rows) {
+            u = R + static_cast<int>(t / w);
+            v = static_cast<int>(t % w);
+          } else {
+            const int64_t t2 = t - strip_rows;
+            u = static_cast<int>(t2 / (w - R));
+            v = R + static_cast<int>(t2 % (w - R));
+          }
+        } else {
+          const int64_t b = t - strip;
+          const int by = static_cast<int>(b / nb);
+          const int bx = static_cast<int>(b - static_cast<int64_t>(by) * nb);
+          const int32_t tt = table[static_cast<int64_t>(beta) * beta - 1];
+          u = by * beta + (tt >> 16);
+          v = bx * beta + (tt & 0xffff);
+        }
+        int y = u + dy, x = v + dx;
+        if (y >= w) y -= w;
+        if (x >= w) x -= w;
+        p = static_cast<int64_t>(y) * w + x;
+      }
+      cell[0] = cell[1] = cell[2] = cell[3] = p;
+    }
+
+    float4 g[4], tg[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      g[i] = G4[cell[i] * LG + sub];
+      tg[i] = T4[cell[i] * LG + sub];
+    }
+    // Pair q = 4i + j: grid cell i against target cell j.
+    float part[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) part[4 * i + j] = chunk_sq(g[i], tg[j]);
+#pragma unroll
+    for (int b = 0; b < LEVELS; ++b) {
+      const bool upper = (sub >> b) & 1;
+#pragma unroll
+      for (int t = 0; t < (8 >> b); ++t) {
+        const float lo = part[2 * t], hi = part[2 * t + 1];
+        const float keep = upper ? hi : lo;
+        const float give = upper ? lo : hi;
+        part[t] = keep + __shfl_xor(give, 1 << b);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < KEEP; ++t)
+      q_item[t * LG + sub] = static_cast<unsigned long long>(static_cast<double>(part[t]) * scale);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // Orderings sub, sub + LG, ...: this lane's first minimum.
+    unsigned long long best = ~0ull;
+    int best_m = 24;
+#pragma unroll
+    for (int m0 = 0; m0 < 24; m0 += LG) {
+      const int m = m0 + sub;
+      if (m < 24) {
+        const uint32_t code = order_code(m);
+        const unsigned long long cost = q_item[0 + (code & 3)] + q_item[4 + ((code >> 2) & 3)] +
+                                        q_item[8 + ((code >> 4) & 3)] + q_item[12 + ((code >> 6) & 3)];
+        if (cost < best) {
+          best = cost;
+          best_m = m;
+        }
+      }
+    }
+    // First minimum across the item's lanes: smaller cost, then smaller index.
+#pragma unroll
+    for (int b = 0; b < LEVELS; ++b) {
+      const unsigned long long oc = __shfl_xor(best, 1 << b);
+      const int om = __shfl_xor(best_m, 1 << b);
+      if (oc < best || (oc == best && om < best_m)) {
+        best = oc;
+        best_m = om;
+      }
+    }
+    const unsigned long long self_cost = q_item[0];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    if (is_group && best_m != 0) {
+      const uint32_t code = order_code(best_m);
+      int32_t old_perm[4];
+      if (sub == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) old_perm[i] = P[cell[i]];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int to = (code >> (2 * i)) & 3;
+        if (to != i) {
+          const int64_t dst = to == 0 ? cell[0] : to == 1 ? cell[1] : to == 2 ? cell[2] : cell[3];
+          Gout[dst * LG + sub] = g[i];
+          if (sub == 0) {
+            P[dst] = old_perm[i];
+            ++m_acc;
+          }
+        }
+      }
+    }
+    if (active && sub == 0) e_acc += is_group ? best : self_cost;
+  }
+  e_acc = wave_sum_u64(e_acc);
+  m_acc = wave_sum_u64(m_acc);
+  if (lane == 0) {
+    const int slot_acc = static_cast<int>(wave % kAccSlots);
+    atomicAdd(&st->energy_acc[slot_acc], e_acc);
+    atomicAdd(&st->moved_acc[slot_acc], m_acc);
+  }
+}
+
 // ----------------------------------------------------------------- energy
 
 template <int DP>
@@ -591,7 +879,12 @@ hipError_t launch_assign(float* G, const float* T, int32_t* P, const int32_t* ta
   const int64_t items_per_wave = 64 / (dp / 4);
   const int64_t waves = (max_items + items_per_wave - 1) / items_per_wave;
   const int blocks = blocks_for(waves * 64);
-  PLAS_DISPATCH_DP(dp, (k_assign<DPV><<<blocks, kBlock, 0, stream>>>(G, T, P, table, st)));
+  static const bool v1 = getenv("PLAS_ASSIGN_V1") != nullptr;
+  if (v1) {
+    PLAS_DISPATCH_DP(dp, (k_assign<DPV><<<blocks, kBlock, 0, stream>>>(G, T, P, table, st)));
+  } else {
+    PLAS_DISPATCH_DP(dp, (k_assign2<DPV><<<blocks, kBlock, 0, stream>>>(G, T, P, table, st)));
+  }
   return hipGetLastError();
 }
 
