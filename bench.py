@@ -75,6 +75,12 @@ def main() -> int:
     ap.add_argument("--side", type=int, default=1024)
     ap.add_argument("--cpu-sample-reorders", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-reorders", type=int, default=0,
+                    help="stop each sort after this many reorders (profiling runs only; "
+                         "the JSON line is then not the workload's throughput)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain elementwise copy of 256 MiB (read and write 2^26 "
+                         "floats) to calibrate HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the PLAS sort of one grid is a single-device "
@@ -97,8 +103,16 @@ def main() -> int:
     ctx = plas.Context(0)
     torch.cuda.synchronize()
 
+    if args.copy_probe:
+        src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 launches, each reads {src.numel() * 4} B and writes {dst.numel() * 4} B")
+        del src, dst
     for i in range(args.warmup):
-        _, res = ctx.sort(f_dev, side, seed, out=perm)
+        _, res = ctx.sort(f_dev, side, seed, out=perm, max_reorders=args.max_reorders)
         log(f"warmup {i}: {res.reorders} reorders, {res.levels} levels, {res.total_ms:.1f} ms")
     torch.cuda.synchronize()
 
@@ -108,7 +122,7 @@ def main() -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, res = ctx.sort(f_dev, side, seed, out=perm, profile=True)
+        _, res = ctx.sort(f_dev, side, seed, out=perm, profile=True, max_reorders=args.max_reorders)
         results.append(res)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -163,7 +177,10 @@ def main() -> int:
         },
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
+    if args.max_reorders:
+        line["config"]["max_reorders"] = args.max_reorders
+        line["note"] = "truncated profiling run, not the workload's throughput"
+    if not args.no_cpu_baseline and not args.max_reorders:
         line["cpu_baseline"] = cpu_baseline(F, side, seed, res.reorders, args.cpu_sample_reorders)
     print(json.dumps(line), flush=True)
     return 0

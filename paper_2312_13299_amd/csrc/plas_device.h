@@ -50,6 +50,8 @@ struct DevState {
   int32_t just_shifted;
   int32_t levels_run;
   uint32_t inv_threshold;
+  int32_t pending;  // a reorder has run whose result the controller has not seen
+  int32_t pad;
   int64_t k;  // reorders done
   int64_t max_reorders;
   int64_t level_reorders;

@@ -56,7 +56,7 @@ struct plas_context {
   DeviceBuffer range_part, range_out;   // range pass scratch and result
   DeviceBuffer levels;                  // LevelInfo[levels]
   DeviceBuffer trace;                   // plas_level_out[levels]
-  DeviceBuffer state;                   // DevState of a sort
+  DeviceBuffer state;                   // two DevStates of a sort (read one, write the other)
   DeviceBuffer stage_state;             // DevState of a stage call
   DeviceBuffer scratch;                 // u64 accumulators and flags
   // Pinned host memory for small read-backs.
@@ -321,7 +321,7 @@ int32_t plas_create(plas_handle* out, int32_t device) {
             hipHostMalloc(reinterpret_cast<void**>(&h->range_host), (2 * 64 + 1) * sizeof(float)) == hipSuccess &&
             hipHostMalloc(reinterpret_cast<void**>(&h->u64_host), 16 * sizeof(unsigned long long)) == hipSuccess &&
             hipHostMalloc(reinterpret_cast<void**>(&h->state_host), sizeof(DevState)) == hipSuccess &&
-            reserve(h->state, sizeof(DevState)) == hipSuccess &&
+            reserve(h->state, 2 * sizeof(DevState)) == hipSuccess &&
             reserve(h->stage_state, sizeof(DevState)) == hipSuccess &&
             reserve(h->scratch, 16 * sizeof(unsigned long long)) == hipSuccess;
   if (!ok) {
@@ -439,12 +439,15 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
   S->j = 1;
   const plas::Words4 keys = plas::draw(prm.seed, plas::kDrawGrouping, 0);
   for (int i = 0; i < 4; ++i) S->keys[i] = keys.v[i];
-  DevState* Sd = as<DevState>(h->state);
-  PLAS_HIP(h, hipMemcpyAsync(Sd, S, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
+  // State buffers: each reorder's step launch reads states[cur] and writes
+  // states[cur ^ 1], which the reorder's kernels then use.
+  DevState* states = as<DevState>(h->state);
+  int cur = 0;
+  PLAS_HIP(h, hipMemcpyAsync(&states[0], S, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
 
   const LevelInfo* Ld = as<LevelInfo>(h->levels);
   plas_level_out* Td = as<plas_level_out>(h->trace);
-  const int32_t* table = as<int32_t>(h->table);
+  int32_t* table = as<int32_t>(h->table);
   const int chunk = prm.reorders_per_sync > 0 ? prm.reorders_per_sync : kDefaultReordersPerSync;
   const bool profile = prm.profile != 0;
   if (profile) {
@@ -456,25 +459,34 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
       static_cast<int64_t>(levels.size()) * (static_cast<int64_t>(prm.inv_threshold) * 44 + 3);
   double blur_ms = 0.0, assign_ms = 0.0;
   int64_t timed_reorders = 0;
-  int64_t k_seen = 0;
+  int64_t slots = 0;  // reorder slots queued so far; slot i runs reorder i unless the sort has ended
   for (;;) {
     for (int i = 0; i < chunk; ++i) {
+      DevState* Sd = &states[cur ^ 1];
+      PLAS_HIP(h, plas::launch_step(&states[cur], Sd, Ld, Td, table, max_cells, h->stream));
+      cur ^= 1;
       if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 0], h->stream));
       PLAS_HIP(h, plas::launch_blur_pass(G, H, w, dp, Sd, 0, 0, as<float>(h->inv), h->stream));
       PLAS_HIP(h, plas::launch_blur_pass(H, T, w, dp, Sd, 0, 1, as<float>(h->inv), h->stream));
       if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 1], h->stream));
-      PLAS_HIP(h, plas::launch_group_table(as<int32_t>(h->table), Sd, max_cells, h->stream));
       if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 2], h->stream));
       PLAS_HIP(h, plas::launch_assign(G, T, P, table, Sd, dp, max_items, h->stream));
       if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 3], h->stream));
-      PLAS_HIP(h, plas::launch_control(Sd, Ld, Td, h->stream));
     }
-    PLAS_HIP(h, hipMemcpyAsync(h->status_host, &Sd->done, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-    PLAS_HIP(h, hipMemcpyAsync(&h->status_host->k, &Sd->k, sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
+    const int64_t first_slot = slots;
+    slots += chunk;
+    // The control step of a chunk's last reorder runs at the start of the
+    // next chunk, so `k` read here may lag the queued reorders by one.
+    PLAS_HIP(h, hipMemcpyAsync(h->status_host, &states[cur].done, sizeof(int32_t), hipMemcpyDeviceToHost,
+                               h->stream));
+    PLAS_HIP(h, hipMemcpyAsync(&h->status_host->k, &states[cur].k, sizeof(int64_t), hipMemcpyDeviceToHost,
+                               h->stream));
     PLAS_HIP(h, hipStreamSynchronize(h->stream));
+    const bool done = h->status_host->done != 0;
+    const int64_t k_now = h->status_host->k;
     if (profile) {
-      // Only the reorders that ran count; the rest of the chunk returned at once.
-      const int64_t ran = std::min<int64_t>(chunk, h->status_host->k - k_seen);
+      // Slots at or after the end of the sort returned at once.
+      const int64_t ran = done ? std::max<int64_t>(0, std::min<int64_t>(chunk, k_now - first_slot)) : chunk;
       for (int64_t i = 0; i < ran; ++i) {
         float a = 0.0f, b = 0.0f;
         PLAS_HIP(h, hipEventElapsedTime(&a, h->events[4 * i + 0], h->events[4 * i + 1]));
@@ -484,19 +496,18 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
       }
       timed_reorders += ran;
     }
-    if (h->status_host->done) break;
-    // Each queued reorder either runs (k grows) or finds the sort done, so a
-    // chunk that leaves k unchanged without done means the device state is
-    // broken; also stop at the bound on reorders that the stall test implies
-    // (energies strictly fall by at least 1/M per improvement).
-    if (h->status_host->k == k_seen || h->status_host->k > reorder_bound)
+    if (done) break;
+    // Every queued slot but the last has been controlled by now; if k falls
+    // short the device state is broken. Also stop at the bound on reorders
+    // that the stall test implies (energies strictly fall by at least 1/M per
+    // improvement, two stalls end a level).
+    if (k_now < slots - 1 || k_now > reorder_bound)
       return fail(h, PLAS_ERR_HIP, "device controller made no progress");
-    k_seen = h->status_host->k;
   }
 
   PLAS_HIP(h, hipMemcpyAsync(perm_out, P, static_cast<size_t>(n) * sizeof(int32_t), hipMemcpyDeviceToDevice,
                              h->stream));
-  PLAS_HIP(h, hipMemcpyAsync(S, Sd, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+  PLAS_HIP(h, hipMemcpyAsync(S, &states[cur], sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
   PLAS_HIP(h, hipStreamSynchronize(h->stream));
   if (stats != nullptr) {
     stats->levels = S->levels_run;

@@ -13,8 +13,6 @@
 // equal, bit for bit, to a CPU that evaluates the same expressions.
 #include <hip/hip_runtime.h>
 
-#include <cstdlib>
-
 #include "plas_launch.h"
 #include "plas_random.h"
 
@@ -182,6 +180,15 @@ __global__ __launch_bounds__(kBlock) void k_gather(const float* __restrict__ X, 
 
 // ------------------------------------------------------------------- blur
 
+// Orders this wave's LDS writes before its later LDS reads (lanes of one
+// wave exchange data through LDS without a block barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+
 // One separable box-blur pass. Lane = (line, channel): DP consecutive lanes
 // walk one line, 64 / DP lines per wave. Along the line the window sum is
 // kept as a running sum: it starts as the ascending sum of the first
@@ -313,16 +320,222 @@ __global__ __launch_bounds__(kBlock) void k_blur(const float* __restrict__ in, f
   }
 }
 
+// Blur pass for 64-channel cells, staged through LDS. Same arithmetic as
+// k_blur (one running sum per line and channel, same operation order), but
+// the memory side is reorganised: a dword load per position can only keep
+// one position of 64 chains in flight per instruction, which caps the bytes
+// in flight far below what HBM needs. Here every lane loads 16 bytes
+// (4 channels) of one of 4 consecutive positions, so one instruction brings
+// 4 positions (1 KB) of the wave's line; kStageChunk positions of the
+// entering and of the leaving stream go through LDS, where lane = channel
+// reads them back in order. Outputs return through LDS and leave as 16-byte
+// stores. The loads of the next kStageDepth - 1 chunks are in flight while
+// the current one is summed. One wave per line, four lines per block.
+constexpr int kStageChunk = 32;
+constexpr int kStageVec = kStageChunk / 4;
+constexpr int kStageDepth = 4;  // chunks whose loads are in flight
+
+struct StagedRegs {
+  float4 enter[kStageVec];
+  float4 leave[kStageVec];
+  float mult;  // lane p < kStageChunk: float32(1/count) of the chunk's position p
+};
+
+struct StagedLine {
+  const float* __restrict__ src;
+  float* __restrict__ dst;
+  const float* __restrict__ inv;
+  int64_t step;
+  int w, r, first_hi, n_init;
+  int q, j, lane;
+  float (*s_enter)[64];
+  float (*s_leave)[64];
+  float (*s_out)[64];
+
+  __device__ __forceinline__ float4 ld(int t) const {
+    return reinterpret_cast<const float4*>(src + static_cast<int64_t>(t) * step)[j];
+  }
+
+  // Chunks 0 .. n_init-1 cover positions 0 .. first_hi of the starting sum;
+  // chunk n_init + k covers output positions 1 + k*kStageChunk onwards.
+  __device__ __forceinline__ void fetch(int c, StagedRegs& R) const {
+    const float4 zero = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (c < n_init) {
+#pragma unroll
+      for (int i = 0; i < kStageVec; ++i) {
+        const int t = c * kStageChunk + 4 * i + q;
+        R.enter[i] = t <= first_hi ? ld(t) : zero;
+        R.leave[i] = zero;
+      }
+      R.mult = 0.0f;
+    } else {
+      const int x0 = 1 + (c - n_init) * kStageChunk;
+#pragma unroll
+      for (int i = 0; i < kStageVec; ++i) {
+        const int x = x0 + 4 * i + q;
+        const int a = x + r, b = x - r - 1;
+        R.enter[i] = (x < w && a <= w - 1) ? ld(a) : zero;
+        R.leave[i] = (x < w && b >= 0) ? ld(b) : zero;
+      }
+      const int x = x0 + (lane & (kStageChunk - 1));
+      const int hi = x + r < w - 1 ? x + r : w - 1;
+      const int lo = x - r > 0 ? x - r : 0;
+      R.mult = x < w ? inv[hi - lo + 1] : 0.0f;
+    }
+  }
+
+  // Output positions x0 .. x0 + kStageChunk - 1, all inside the grid, all
+  // with (ENTER) or without an entering value and all with (LEAVE) or
+  // without a leaving one: no per-position tests.
+  template <bool ENTER, bool LEAVE>
+  __device__ __forceinline__ void run_uniform(int mult_bits, float& s) const {
+    float e[kStageChunk], l[kStageChunk];
+#pragma unroll
+    for (int p = 0; p < kStageChunk; ++p) {
+      if (ENTER) e[p] = s_enter[p][lane];
+      if (LEAVE) l[p] = s_leave[p][lane];
+    }
+#pragma unroll
+    for (int p = 0; p < kStageChunk; ++p) {
+      if (ENTER) s = s + e[p];
+      if (LEAVE) s = s - l[p];
+      s_out[p][lane] = s * __int_as_float(__builtin_amdgcn_readlane(mult_bits, p));
+    }
+  }
+
+  // Any chunk: the tests of each position select the update.
+  __device__ __forceinline__ void run_mixed(int x0, int mult_bits, float& s) const {
+    float e[kStageChunk], l[kStageChunk];
+#pragma unroll
+    for (int p = 0; p < kStageChunk; ++p) {
+      e[p] = s_enter[p][lane];
+      l[p] = s_leave[p][lane];
+    }
+#pragma unroll
+    for (int p = 0; p < kStageChunk; ++p) {
+      const int x = x0 + p;
+      const bool inside = x < w;
+      const float with_enter = s + e[p];
+      s = (inside && x + r <= w - 1) ? with_enter : s;
+      const float with_leave = s - l[p];
+      s = (inside && x - r - 1 >= 0) ? with_leave : s;
+      s_out[p][lane] = s * __int_as_float(__builtin_amdgcn_readlane(mult_bits, p));
+    }
+  }
+
+  // Lanes exchange the staged values through LDS. DS instructions of one
+  // wave execute in issue order, and every LDS read below may alias an
+  // earlier LDS write in the compiler's view, so program order suffices.
+  __device__ __forceinline__ void consume(int c, const StagedRegs& R, float& s) const {
+#pragma unroll
+    for (int i = 0; i < kStageVec; ++i) {
+      *reinterpret_cast<float4*>(&s_enter[4 * i + q][4 * j]) = R.enter[i];
+      *reinterpret_cast<float4*>(&s_leave[4 * i + q][4 * j]) = R.leave[i];
+    }
+    if (c < n_init) {
+      const int t0 = c * kStageChunk;
+      float e[kStageChunk];
+#pragma unroll
+      for (int p = 0; p < kStageChunk; ++p) e[p] = s_enter[p][lane];
+      if (t0 > 0 && t0 + kStageChunk - 1 <= first_hi) {
+#pragma unroll
+        for (int p = 0; p < kStageChunk; ++p) s = s + e[p];
+      } else {
+#pragma unroll
+        for (int p = 0; p < kStageChunk; ++p) {
+          const int t = t0 + p;
+          const float added = t == 0 ? e[p] : s + e[p];
+          s = t <= first_hi ? added : s;
+        }
+      }
+      if (c == n_init - 1) dst[lane] = s * inv[first_hi + 1];
+      return;
+    }
+    const int x0 = 1 + (c - n_init) * kStageChunk;
+    const int x1 = x0 + kStageChunk - 1;
+    const int mult_bits = __float_as_int(R.mult);
+    // Position x has an entering value iff x + r <= w - 1 and a leaving
+    // value iff x - r - 1 >= 0.
+    const bool all_in = x1 < w;
+    const bool enter_all = x1 + r <= w - 1, enter_none = x0 + r > w - 1;
+    const bool leave_all = x0 - r - 1 >= 0, leave_none = x1 - r - 1 < 0;
+    if (all_in && enter_all && leave_all)
+      run_uniform<true, true>(mult_bits, s);
+    else if (all_in && enter_all && leave_none)
+      run_uniform<true, false>(mult_bits, s);
+    else if (all_in && enter_none && leave_all)
+      run_uniform<false, true>(mult_bits, s);
+    else if (all_in && enter_none && leave_none)
+      run_uniform<false, false>(mult_bits, s);
+    else
+      run_mixed(x0, mult_bits, s);
+#pragma unroll
+    for (int i = 0; i < kStageVec; ++i) {
+      const int x = x0 + 4 * i + q;
+      if (x < w)
+        reinterpret_cast<float4*>(dst + static_cast<int64_t>(x) * step)[j] =
+            *reinterpret_cast<const float4*>(&s_out[4 * i + q][4 * j]);
+    }
+  }
+};
+
+__global__ __launch_bounds__(kBlock) void k_blur_staged64(const float* __restrict__ in, float* __restrict__ out,
+                                                          int w, const DevState* __restrict__ st, int radius,
+                                                          int vertical, const float* __restrict__ inv) {
+  __shared__ float s_stage[kWavesPerBlock][3][kStageChunk][64];
+  if (st != nullptr && st->done) return;
+  const int r = st != nullptr ? st->r : radius;
+  const int wib = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t line = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wib;
+  if (line >= w) return;  // no block-wide barriers follow
+  StagedLine L;
+  const int64_t base = vertical ? line * 64 : line * w * 64;
+  L.src = in + base;
+  L.dst = out + base;
+  L.inv = inv;
+  L.step = vertical ? static_cast<int64_t>(w) * 64 : 64;
+  L.w = w;
+  L.r = r;
+  L.q = lane >> 4;
+  L.j = lane & 15;
+  L.lane = lane;
+  L.s_enter = s_stage[wib][0];
+  L.s_leave = s_stage[wib][1];
+  L.s_out = s_stage[wib][2];
+  if (r == 0) {
+    for (int x = 0; x < w; ++x) L.dst[x * L.step + lane] = L.src[x * L.step + lane];
+    return;
+  }
+  L.first_hi = r < w - 1 ? r : w - 1;
+  L.n_init = (L.first_hi + kStageChunk) / kStageChunk;
+  const int n_chunks = L.n_init + (w - 1 + kStageChunk - 1) / kStageChunk;
+  // A ring of kStageDepth register chunks: chunk c + kStageDepth - 1 is
+  // requested before chunk c is summed.
+  float s = 0.0f;
+  StagedRegs ring[kStageDepth];
+#pragma unroll
+  for (int b = 0; b < kStageDepth - 1; ++b)
+    if (b < n_chunks) L.fetch(b, ring[b]);
+  for (int c0 = 0; c0 < n_chunks; c0 += kStageDepth) {
+#pragma unroll
+    for (int b = 0; b < kStageDepth; ++b) {
+      const int c = c0 + b;
+      if (c >= n_chunks) break;
+      const int ahead = c + kStageDepth - 1;
+      if (ahead < n_chunks) L.fetch(ahead, ring[(b + kStageDepth - 1) % kStageDepth]);
+      L.consume(c, ring[b], s);
+    }
+  }
+}
+
 // ---------------------------------------------------------- group table
 
 // table[t] = pi(t) packed as (ly << 16) | lx, pi the grouping bijection of
-// the current reorder over the beta^2 block-local cells.
-__global__ __launch_bounds__(kBlock) void k_group_table(int32_t* __restrict__ table,
-                                                        const DevState* __restrict__ st) {
-  if (st->done) return;
-  const int beta = st->beta;
+// a reorder over the beta^2 block-local cells, filled by all blocks.
+__device__ __forceinline__ void fill_group_table(int32_t* __restrict__ table, int beta, const uint64_t keys[4]) {
   const uint64_t cells = static_cast<uint64_t>(beta) * beta;
-  const Bijection f(cells, st->keys);
+  const Bijection f(cells, keys);
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kBlock;
   for (uint64_t t = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; t < cells; t += stride) {
     const uint32_t v = static_cast<uint32_t>(f(t));
@@ -332,7 +545,11 @@ __global__ __launch_bounds__(kBlock) void k_group_table(int32_t* __restrict__ ta
   }
 }
 
-// ------------------------------------------------------------- assignment
+__global__ __launch_bounds__(kBlock) void k_group_table(int32_t* __restrict__ table,
+                                                        const DevState* __restrict__ st) {
+  if (st->done) return;
+  fill_group_table(table, st->beta, st->keys);
+}
 
 // Squared distance partial over one lane's 4 channels, as the two lowest
 // levels of the pairwise tree: (c0^2 + c1^2) + (c2^2 + c3^2).
@@ -347,168 +564,6 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
   return v;
 }
 
-// Position code of an ordering: sigma(i) in bits 2i..2i+1.
-#define PLAS_CODE(a, b, c, e) ((a) | ((b) << 2) | ((c) << 4) | ((e) << 6))
-#define PLAS_TRY(a, b, c, e)                                                  \
-  {                                                                           \
-    const unsigned long long cost_ = q[0][a] + q[1][b] + q[2][c] + q[3][e];   \
-    if (cost_ < best) {                                                       \
-      best = cost_;                                                           \
-      code = PLAS_CODE(a, b, c, e);                                           \
-    }                                                                         \
-  }
-
-// One reorder's blockwise assignment. Items are the groups of every block
-// (item < groups) followed by the cells in no group (singles), whose
-// distance still counts towards the energy. LG = DP/4 lanes serve one item:
-// lane `sub` holds channels 4*sub .. 4*sub+3 of the item's four grid cells
-// and four target cells and forms all 16 pair partials; xor-butterflies over
-// the LG lanes complete the pairwise channel tree (level by level, left half
-// plus right half), so every lane ends with the 16 exact distances.
-template <int DP>
-__global__ __launch_bounds__(kBlock) void k_assign(float* __restrict__ G, const float* __restrict__ T,
-                                                   int32_t* __restrict__ P,
-                                                   const int32_t* __restrict__ table,
-                                                   DevState* __restrict__ st) {
-  if (st->done) return;
-  constexpr int LG = DP / 4;
-  constexpr int IPW = 64 / LG;
-  const int w = st->w, beta = st->beta, nb = st->nb, dy = st->dy, dx = st->dx;
-  const int64_t gpb = st->groups_per_block;
-  const int64_t groups = st->groups;
-  const int64_t total = groups + st->singles;
-  const double scale = ldexp(1.0, st->s);
-  const int lane = threadIdx.x & 63;
-  const int sub = lane % LG, slot = lane / LG;
-  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 6;
-  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * kBlock) >> 6;
-  const int R = nb * beta;
-  const int64_t strip_rows = static_cast<int64_t>(w - R) * w;
-  const int64_t strip = static_cast<int64_t>(w) * w - static_cast<int64_t>(R) * R;
-  const float4* __restrict__ G4 = reinterpret_cast<const float4*>(G);
-  const float4* __restrict__ T4 = reinterpret_cast<const float4*>(T);
-  float4* __restrict__ Gout = reinterpret_cast<float4*>(G);
-  unsigned long long e_acc = 0, m_acc = 0;
-
-  for (int64_t first = wave * IPW; first < total; first += nwaves * IPW) {
-    const int64_t item = first + slot;
-    const bool active = item < total;
-    const bool is_group = item < groups;
-    int64_t cell[4];
-    if (is_group) {
-      const int64_t b = item / gpb;
-      const int64_t g = item - b * gpb;
-      const int by = static_cast<int>(b / nb);
-      const int bx = static_cast<int>(b - static_cast<int64_t>(by) * nb);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int32_t t = table[4 * g + i];
-        int y = dy + by * beta + (t >> 16);
-        int x = dx + bx * beta + (t & 0xffff);
-        if (y >= w) y -= w;
-        if (x >= w) x -= w;
-        cell[i] = static_cast<int64_t>(y) * w + x;
-      }
-    } else {
-      int64_t p = 0;
-      if (active) {
-        const int64_t t = item - groups;
-        int u, v;
-        if (t < strip) {
-          // Rolled-grid cells outside the nb*beta square: first the full
-          // rows below it, then the columns right of it.
-          if (t < strip_rows) {
-            u = R + static_cast<int>(t / w);
-            v = static_cast<int>(t % w);
-          } else {
-            const int64_t t2 = t - strip_rows;
-            u = static_cast<int>(t2 / (w - R));
-            v = R + static_cast<int>(t2 % (w - R));
-          }
-        } else {
-          // The left-over cell pi(beta^2 - 1) of each block (odd beta).
-          const int64_t b = t - strip;
-          const int by = static_cast<int>(b / nb);
-          const int bx = static_cast<int>(b - static_cast<int64_t>(by) * nb);
-          const int32_t tt = table[static_cast<int64_t>(beta) * beta - 1];
-          u = by * beta + (tt >> 16);
-          v = bx * beta + (tt & 0xffff);
-        }
-        int y = u + dy, x = v + dx;
-        if (y >= w) y -= w;
-        if (x >= w) x -= w;
-        p = static_cast<int64_t>(y) * w + x;
-      }
-      cell[0] = cell[1] = cell[2] = cell[3] = p;
-    }
-
-    float4 g[4], tg[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      g[i] = G4[cell[i] * LG + sub];
-      tg[i] = T4[cell[i] * LG + sub];
-    }
-    float d[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) d[i][j] = chunk_sq(g[i], tg[j]);
-#pragma unroll
-    for (int m = 1; m < LG; m <<= 1)
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) d[i][j] = d[i][j] + __shfl_xor(d[i][j], m);
-
-    unsigned long long q[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        q[i][j] = static_cast<unsigned long long>(static_cast<double>(d[i][j]) * scale);
-
-    // First minimum over the 24 orderings in lexicographic order.
-    unsigned long long best = q[0][0] + q[1][1] + q[2][2] + q[3][3];
-    uint32_t code = PLAS_CODE(0, 1, 2, 3);
-    PLAS_TRY(0, 1, 3, 2) PLAS_TRY(0, 2, 1, 3) PLAS_TRY(0, 2, 3, 1) PLAS_TRY(0, 3, 1, 2)
-    PLAS_TRY(0, 3, 2, 1) PLAS_TRY(1, 0, 2, 3) PLAS_TRY(1, 0, 3, 2) PLAS_TRY(1, 2, 0, 3)
-    PLAS_TRY(1, 2, 3, 0) PLAS_TRY(1, 3, 0, 2) PLAS_TRY(1, 3, 2, 0) PLAS_TRY(2, 0, 1, 3)
-    PLAS_TRY(2, 0, 3, 1) PLAS_TRY(2, 1, 0, 3) PLAS_TRY(2, 1, 3, 0) PLAS_TRY(2, 3, 0, 1)
-    PLAS_TRY(2, 3, 1, 0) PLAS_TRY(3, 0, 1, 2) PLAS_TRY(3, 0, 2, 1) PLAS_TRY(3, 1, 0, 2)
-    PLAS_TRY(3, 1, 2, 0) PLAS_TRY(3, 2, 0, 1) PLAS_TRY(3, 2, 1, 0)
-
-    if (is_group && code != PLAS_CODE(0, 1, 2, 3)) {
-      int32_t old_perm[4];
-      if (sub == 0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) old_perm[i] = P[cell[i]];
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int to = (code >> (2 * i)) & 3;
-        if (to != i) {
-          const int64_t dst = to == 0 ? cell[0] : to == 1 ? cell[1] : to == 2 ? cell[2] : cell[3];
-          Gout[dst * LG + sub] = g[i];
-          if (sub == 0) {
-            P[dst] = old_perm[i];
-            ++m_acc;
-          }
-        }
-      }
-    }
-    if (active && sub == 0) e_acc += is_group ? best : q[0][0];
-  }
-  e_acc = wave_sum_u64(e_acc);
-  m_acc = wave_sum_u64(m_acc);
-  if (lane == 0) {
-    const int slot_acc = static_cast<int>(wave % kAccSlots);
-    atomicAdd(&st->energy_acc[slot_acc], e_acc);
-    atomicAdd(&st->moved_acc[slot_acc], m_acc);
-  }
-}
-
-#undef PLAS_TRY
-#undef PLAS_CODE
 
 // The 24 orderings of (0,1,2,3) in lexicographic order as position codes
 // (sigma(i) in bits 2i..2i+1), eight codes per 64-bit word, ordering m in
@@ -523,8 +578,13 @@ __device__ __forceinline__ uint32_t order_code(int m) {
   return static_cast<uint32_t>((word >> (8 * (m & 7))) & 0xff);
 }
 
-// Assignment, second form. Same items and results as k_assign; the work
-// after the distance partials is split across the LG lanes of an item:
+// One reorder's blockwise assignment. Items are the groups of every block
+// (item < groups) followed by the cells in no group (singles), whose
+// distance still counts towards the energy. LG = DP/4 lanes serve one item:
+// lane `sub` holds channels 4*sub .. 4*sub+3 of the item's four grid cells
+// and four target cells and forms all 16 pair partials as the two lowest
+// levels of the channel tree. The rest of the work is split across the LG
+// lanes:
 //  - a transposed butterfly: at tree level b each lane keeps the pairs whose
 //    bit b matches its own lane bit, adds the partner's partial for them and
 //    hands over the others, so after log2(LG) levels lane L holds the exact
@@ -533,42 +593,18 @@ __device__ __forceinline__ uint32_t order_code(int m) {
 //  - the quantised pair costs go to LDS; lane L evaluates orderings
 //    L, L+LG, ... and the lanes pick the first minimum with a butterfly on
 //    (cost, ordering index).
-template <int DP>
-__global__ __launch_bounds__(kBlock) void k_assign2(float* __restrict__ G, const float* __restrict__ T,
-                                                    int32_t* __restrict__ P,
-                                                    const int32_t* __restrict__ table,
-                                                    DevState* __restrict__ st) {
-  if (st->done) return;
-  constexpr int LG = DP / 4;
-  constexpr int IPW = 64 / LG;
-  constexpr int LEVELS = LG == 1 ? 0 : LG == 2 ? 1 : LG == 4 ? 2 : LG == 8 ? 3 : 4;
-  constexpr int KEEP = 16 / LG;  // pair distances held per lane after the reduction
-  __shared__ unsigned long long s_q[kWavesPerBlock][IPW][16];
-  const int w = st->w, beta = st->beta, nb = st->nb, dy = st->dy, dx = st->dx;
-  const int64_t gpb = st->groups_per_block;
-  const int64_t groups = st->groups;
-  const int64_t total = groups + st->singles;
-  const double scale = ldexp(1.0, st->s);
-  const int lane = threadIdx.x & 63;
-  const int wib = threadIdx.x >> 6;
-  const int sub = lane % LG, slot = lane / LG;
-  unsigned long long* q_item = s_q[wib][slot];
-  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 6;
-  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * kBlock) >> 6;
-  const int R = nb * beta;
-  const int64_t strip_rows = static_cast<int64_t>(w - R) * w;
-  const int64_t strip = static_cast<int64_t>(w) * w - static_cast<int64_t>(R) * R;
-  const float4* __restrict__ G4 = reinterpret_cast<const float4*>(G);
-  const float4* __restrict__ T4 = reinterpret_cast<const float4*>(T);
-  float4* __restrict__ Gout = reinterpret_cast<float4*>(G);
-  unsigned long long e_acc = 0, m_acc = 0;
+// Geometry of one reorder's items, read once per thread.
+struct ItemGeometry {
+  const int32_t* __restrict__ table;
+  int w, beta, nb, dy, dx, R;
+  int64_t gpb, groups, total, strip_rows, strip;
 
-  for (int64_t first = wave * IPW; first < total; first += nwaves * IPW) {
-    const int64_t item = first + slot;
-    const bool active = item < total;
-    const bool is_group = item < groups;
-    int64_t cell[4];
-    if (is_group) {
+  // The four cells of group `item`, or four times the cell of single `item`
+  // (cells in no group: first the rolled-grid rows below the nb*beta square,
+  // then the columns right of it, then the left-over cell pi(beta^2 - 1) of
+  // each block when beta is odd). Inactive items map to cell 0.
+  __device__ __forceinline__ void cells(int64_t item, int32_t cell[4]) const {
+    if (item < groups) {
       const int64_t b = item / gpb;
       const int64_t g = item - b * gpb;
       const int by = static_cast<int>(b / nb);
@@ -580,44 +616,99 @@ __global__ __launch_bounds__(kBlock) void k_assign2(float* __restrict__ G, const
         int x = dx + bx * beta + (t & 0xffff);
         if (y >= w) y -= w;
         if (x >= w) x -= w;
-        cell[i] = static_cast<int64_t>(y) * w + x;
+        cell[i] = y * w + x;
       }
-    } else {
-      int64_t p = 0;
-      if (active) {
-        const int64_t t = item - groups;
-        int u, v;
-        if (t < strip) {
-          if (t < strip_rows) {
-            u = R + static_cast<int>(t / w);
-            v = static_cast<int>(t % w);
-          } else {
-            const int64_t t2 = t - strip_rows;
-            u = static_cast<int>(t2 / (w - R));
-            v = R + static_cast<int>(t2 % (w - R));
-          }
-        } else {
-          const int64_t b = t - strip;
-          const int by = static_cast<int>(b / nb);
-          const int bx = static_cast<int>(b - static_cast<int64_t>(by) * nb);
-          const int32_t tt = table[static_cast<int64_t>(beta) * beta - 1];
-          u = by * beta + (tt >> 16);
-          v = bx * beta + (tt & 0xffff);
-        }
-        int y = u + dy, x = v + dx;
-        if (y >= w) y -= w;
-        if (x >= w) x -= w;
-        p = static_cast<int64_t>(y) * w + x;
-      }
-      cell[0] = cell[1] = cell[2] = cell[3] = p;
+      return;
     }
+    int32_t p = 0;
+    if (item < total) {
+      const int64_t t = item - groups;
+      int u, v;
+      if (t < strip) {
+        if (t < strip_rows) {
+          u = R + static_cast<int>(t / w);
+          v = static_cast<int>(t % w);
+        } else {
+          const int64_t t2 = t - strip_rows;
+          u = static_cast<int>(t2 / (w - R));
+          v = R + static_cast<int>(t2 % (w - R));
+        }
+      } else {
+        const int64_t b = t - strip;
+        const int by = static_cast<int>(b / nb);
+        const int bx = static_cast<int>(b - static_cast<int64_t>(by) * nb);
+        const int32_t tt = table[static_cast<int64_t>(beta) * beta - 1];
+        u = by * beta + (tt >> 16);
+        v = bx * beta + (tt & 0xffff);
+      }
+      int y = u + dy, x = v + dx;
+      if (y >= w) y -= w;
+      if (x >= w) x -= w;
+      p = y * w + x;
+    }
+    cell[0] = cell[1] = cell[2] = cell[3] = p;
+  }
+};
 
+template <int DP>
+__global__ __launch_bounds__(kBlock) void k_assign(float* __restrict__ G, const float* __restrict__ T,
+                                                   int32_t* __restrict__ P,
+                                                   const int32_t* __restrict__ table,
+                                                   DevState* __restrict__ st) {
+  if (st->done) return;
+  constexpr int LG = DP / 4;
+  constexpr int IPW = 64 / LG;
+  constexpr int LEVELS = LG == 1 ? 0 : LG == 2 ? 1 : LG == 4 ? 2 : LG == 8 ? 3 : 4;
+  constexpr int KEEP = 16 / LG;  // pair distances held per lane after the reduction
+  __shared__ unsigned long long s_q[kWavesPerBlock][IPW][16];
+  ItemGeometry geo;
+  geo.table = table;
+  geo.w = st->w;
+  geo.beta = st->beta;
+  geo.nb = st->nb;
+  geo.dy = st->dy;
+  geo.dx = st->dx;
+  geo.R = geo.nb * geo.beta;
+  geo.gpb = st->groups_per_block;
+  geo.groups = st->groups;
+  geo.total = geo.groups + st->singles;
+  geo.strip_rows = static_cast<int64_t>(geo.w - geo.R) * geo.w;
+  geo.strip = static_cast<int64_t>(geo.w) * geo.w - static_cast<int64_t>(geo.R) * geo.R;
+  const double scale = ldexp(1.0, st->s);
+  const int lane = threadIdx.x & 63;
+  const int wib = threadIdx.x >> 6;
+  const int sub = lane % LG, slot = lane / LG;
+  unsigned long long* q_item = s_q[wib][slot];
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * kBlock) >> 6;
+  const float4* __restrict__ G4 = reinterpret_cast<const float4*>(G);
+  const float4* __restrict__ T4 = reinterpret_cast<const float4*>(T);
+  float4* __restrict__ Gout = reinterpret_cast<float4*>(G);
+  unsigned long long e_acc = 0, m_acc = 0;
+
+  // Software pipeline: the next item's cells (table reads) are resolved
+  // while the current item's grid and target cells are in flight.
+  int64_t first = wave * IPW;
+  int32_t cell[4];  // cell indices are below 2^31 (side <= 46340)
+  geo.cells(first + slot, cell);
+  for (; first < geo.total; first += nwaves * IPW) {
+    const int64_t item = first + slot;
+    const bool active = item < geo.total;
+    const bool is_group = item < geo.groups;
     float4 g[4], tg[4];
+    int32_t old_perm[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      g[i] = G4[cell[i] * LG + sub];
-      tg[i] = T4[cell[i] * LG + sub];
+      g[i] = G4[static_cast<int64_t>(cell[i]) * LG + sub];
+      tg[i] = T4[static_cast<int64_t>(cell[i]) * LG + sub];
     }
+    if (sub == 0 && is_group) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) old_perm[i] = P[cell[i]];
+    }
+    int32_t next_cell[4];
+    geo.cells(first + nwaves * IPW + slot, next_cell);
+
     // Pair q = 4i + j: grid cell i against target cell j.
     float part[16];
 #pragma unroll
@@ -638,9 +729,7 @@ __global__ __launch_bounds__(kBlock) void k_assign2(float* __restrict__ G, const
 #pragma unroll
     for (int t = 0; t < KEEP; ++t)
       q_item[t * LG + sub] = static_cast<unsigned long long>(static_cast<double>(part[t]) * scale);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_lds_sync();
 
     // Orderings sub, sub + LG, ...: this lane's first minimum.
     unsigned long long best = ~0ull;
@@ -669,23 +758,16 @@ __global__ __launch_bounds__(kBlock) void k_assign2(float* __restrict__ G, const
       }
     }
     const unsigned long long self_cost = q_item[0];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_lds_sync();
 
     if (is_group && best_m != 0) {
       const uint32_t code = order_code(best_m);
-      int32_t old_perm[4];
-      if (sub == 0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) old_perm[i] = P[cell[i]];
-      }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int to = (code >> (2 * i)) & 3;
         if (to != i) {
-          const int64_t dst = to == 0 ? cell[0] : to == 1 ? cell[1] : to == 2 ? cell[2] : cell[3];
-          Gout[dst * LG + sub] = g[i];
+          const int32_t dst = to == 0 ? cell[0] : to == 1 ? cell[1] : to == 2 ? cell[2] : cell[3];
+          Gout[static_cast<int64_t>(dst) * LG + sub] = g[i];
           if (sub == 0) {
             P[dst] = old_perm[i];
             ++m_acc;
@@ -694,6 +776,8 @@ __global__ __launch_bounds__(kBlock) void k_assign2(float* __restrict__ G, const
       }
     }
     if (active && sub == 0) e_acc += is_group ? best : self_cost;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cell[i] = next_cell[i];
   }
   e_acc = wave_sum_u64(e_acc);
   m_acc = wave_sum_u64(m_acc);
@@ -733,73 +817,101 @@ __global__ __launch_bounds__(kBlock) void k_energy(const float* __restrict__ G, 
 
 // -------------------------------------------------------------- controller
 
-// Runs once after each reorder (Sec. 3.1): E is compared with the previous
-// energy; an improvement of at least ceil(E_prev / M) keeps the level and
-// its block shift; the first stall draws a new shift; a stall right after a
-// new shift ends the level (phi <- decay * phi, precomputed in `levels`).
-__global__ void k_control(DevState* __restrict__ st, const LevelInfo* __restrict__ levels,
-                          plas_level_out* __restrict__ trace) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (st->done) return;
+// The control step after each reorder (Sec. 3.1), applied to a state copy:
+// E is compared with the previous energy; an improvement of at least
+// ceil(E_prev / M) keeps the level and its block shift; the first stall
+// draws a new shift; a stall right after a new shift ends the level
+// (phi <- decay * phi, precomputed in `levels`). trace may be NULL.
+__device__ void control_step(DevState& st, const LevelInfo* __restrict__ levels,
+                             plas_level_out* __restrict__ trace) {
   unsigned long long E = 0, moved = 0;
   for (int i = 0; i < kAccSlots; ++i) {
-    E += st->energy_acc[i];
-    moved += st->moved_acc[i];
-    st->energy_acc[i] = 0;
-    st->moved_acc[i] = 0;
+    E += st.energy_acc[i];
+    moved += st.moved_acc[i];
   }
-  st->k += 1;
-  st->level_reorders += 1;
-  st->level_moved += moved;
-  st->energy_last = E;
-  if (st->level_reorders == 1) st->levels_run += 1;
-  const int L = st->level;
-  plas_level_out& tr = trace[L];
-  tr.phi = levels[L].phi;
-  tr.r = levels[L].r;
-  tr.beta = levels[L].beta;
-  tr.reorders = st->level_reorders;
-  tr.energy_fixed = E;
-  tr.moved = st->level_moved;
-
-  const uint64_t M = st->inv_threshold;
-  const uint64_t prev = st->energy_prev;
-  const bool improved = !st->has_prev || (E < prev && prev - E >= (prev + M - 1) / M);
+  st.k += 1;
+  st.level_reorders += 1;
+  st.level_moved += moved;
+  st.energy_last = E;
+  if (st.level_reorders == 1) st.levels_run += 1;
+  const int L = st.level;
+  if (trace != nullptr) {
+    plas_level_out& tr = trace[L];
+    tr.phi = levels[L].phi;
+    tr.r = levels[L].r;
+    tr.beta = levels[L].beta;
+    tr.reorders = st.level_reorders;
+    tr.energy_fixed = E;
+    tr.moved = st.level_moved;
+  }
+  const uint64_t M = st.inv_threshold;
+  const uint64_t prev = st.energy_prev;
+  const bool improved = !st.has_prev || (E < prev && prev - E >= (prev + M - 1) / M);
   if (improved) {
-    st->energy_prev = E;
-    st->has_prev = 1;
-    st->just_shifted = 0;
-  } else if (st->just_shifted) {
+    st.energy_prev = E;
+    st.has_prev = 1;
+    st.just_shifted = 0;
+  } else if (st.just_shifted) {
     const int next = L + 1;
-    if (next >= st->nlevels) {
-      st->done = 1;
+    if (next >= st.nlevels) {
+      st.done = 1;
     } else {
       const LevelInfo lv = levels[next];
-      st->level = next;
-      st->r = lv.r;
-      st->beta = lv.beta;
-      st->nb = lv.nb;
-      st->groups_per_block = lv.groups_per_block;
-      st->groups = lv.groups;
-      st->singles = lv.singles;
-      block_shift(st->seed, st->j, st->w, &st->dy, &st->dx);
-      st->j += 1;
-      st->has_prev = 0;
-      st->just_shifted = 0;
-      st->level_reorders = 0;
-      st->level_moved = 0;
+      st.level = next;
+      st.r = lv.r;
+      st.beta = lv.beta;
+      st.nb = lv.nb;
+      st.groups_per_block = lv.groups_per_block;
+      st.groups = lv.groups;
+      st.singles = lv.singles;
+      block_shift(st.seed, st.j, st.w, &st.dy, &st.dx);
+      st.j += 1;
+      st.has_prev = 0;
+      st.just_shifted = 0;
+      st.level_reorders = 0;
+      st.level_moved = 0;
     }
   } else {
-    block_shift(st->seed, st->j, st->w, &st->dy, &st->dx);
-    st->j += 1;
-    st->just_shifted = 1;
-    st->energy_prev = E;
+    block_shift(st.seed, st.j, st.w, &st.dy, &st.dx);
+    st.j += 1;
+    st.just_shifted = 1;
+    st.energy_prev = E;
   }
-  if (st->max_reorders > 0 && st->k >= st->max_reorders) st->done = 1;
-  if (!st->done) {
-    const Words4 keys = draw(st->seed, kDrawGrouping, static_cast<uint64_t>(st->k));
-    for (int i = 0; i < 4; ++i) st->keys[i] = keys.v[i];
+  if (st.max_reorders > 0 && st.k >= st.max_reorders) st.done = 1;
+  if (!st.done) {
+    const Words4 keys = draw(st.seed, kDrawGrouping, static_cast<uint64_t>(st.k));
+    for (int i = 0; i < 4; ++i) st.keys[i] = keys.v[i];
   }
+}
+
+// One launch between reorders: the control step of the reorder that just
+// ran and the grouping table of the next one. The state is double-buffered:
+// every block reads `in` (nothing writes it during this launch) and applies
+// the same control step to its own LDS copy, so all blocks agree on the next
+// beta and keys; block 0 alone writes `out` and the trace.
+__global__ __launch_bounds__(kBlock) void k_step(const DevState* __restrict__ in, DevState* __restrict__ out,
+                                                 const LevelInfo* __restrict__ levels,
+                                                 plas_level_out* __restrict__ trace,
+                                                 int32_t* __restrict__ table) {
+  static_assert(sizeof(DevState) % 4 == 0, "state is copied as 32-bit words");
+  constexpr int kWords = sizeof(DevState) / 4;
+  __shared__ DevState s_st;
+  uint32_t* words = reinterpret_cast<uint32_t*>(&s_st);
+  for (int i = threadIdx.x; i < kWords; i += kBlock) words[i] = reinterpret_cast<const uint32_t*>(in)[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (!s_st.done && s_st.pending) control_step(s_st, levels, blockIdx.x == 0 ? trace : nullptr);
+    s_st.pending = 1;
+    for (int i = 0; i < kAccSlots; ++i) {
+      s_st.energy_acc[i] = 0;
+      s_st.moved_acc[i] = 0;
+    }
+  }
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < kWords; i += kBlock) reinterpret_cast<uint32_t*>(out)[i] = words[i];
+  if (s_st.done) return;
+  fill_group_table(table, s_st.beta, s_st.keys);
 }
 
 }  // namespace
@@ -860,6 +972,11 @@ hipError_t launch_gather(const float* X, const int32_t* P, float* G, int64_t n, 
 
 hipError_t launch_blur_pass(const float* in, float* out, int w, int dp, const DevState* st,
                             int radius, int vertical, const float* inv, hipStream_t stream) {
+  if (dp == 64) {
+    const int blocks = (w + kWavesPerBlock - 1) / kWavesPerBlock;
+    k_blur_staged64<<<blocks, kBlock, 0, stream>>>(in, out, w, st, radius, vertical, inv);
+    return hipGetLastError();
+  }
   const int lines_per_wave = 64 / dp;
   const int64_t waves = (w + lines_per_wave - 1) / lines_per_wave;
   const int blocks = static_cast<int>((waves + kWavesPerBlock - 1) / kWavesPerBlock);
@@ -879,18 +996,13 @@ hipError_t launch_assign(float* G, const float* T, int32_t* P, const int32_t* ta
   const int64_t items_per_wave = 64 / (dp / 4);
   const int64_t waves = (max_items + items_per_wave - 1) / items_per_wave;
   const int blocks = blocks_for(waves * 64);
-  static const bool v1 = getenv("PLAS_ASSIGN_V1") != nullptr;
-  if (v1) {
-    PLAS_DISPATCH_DP(dp, (k_assign<DPV><<<blocks, kBlock, 0, stream>>>(G, T, P, table, st)));
-  } else {
-    PLAS_DISPATCH_DP(dp, (k_assign2<DPV><<<blocks, kBlock, 0, stream>>>(G, T, P, table, st)));
-  }
+  PLAS_DISPATCH_DP(dp, (k_assign<DPV><<<blocks, kBlock, 0, stream>>>(G, T, P, table, st)));
   return hipGetLastError();
 }
 
-hipError_t launch_control(DevState* st, const LevelInfo* levels, plas_level_out* trace,
-                          hipStream_t stream) {
-  k_control<<<1, 64, 0, stream>>>(st, levels, trace);
+hipError_t launch_step(const DevState* in, DevState* out, const LevelInfo* levels, plas_level_out* trace,
+                       int32_t* table, int64_t max_cells, hipStream_t stream) {
+  k_step<<<blocks_for(max_cells, 1024), kBlock, 0, stream>>>(in, out, levels, trace, table);
   return hipGetLastError();
 }
 

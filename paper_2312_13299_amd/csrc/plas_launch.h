@@ -49,10 +49,11 @@ hipError_t launch_group_table(int32_t* table, const DevState* st, int64_t max_ce
 // groups + singles over every level this launch may see.
 hipError_t launch_assign(float* G, const float* T, int32_t* P, const int32_t* table,
                          DevState* st, int dp, int64_t max_items, hipStream_t stream);
-// Controller: reads the reorder's energy, applies the stall test, advances
-// the schedule and prepares the next reorder's parameters.
-hipError_t launch_control(DevState* st, const LevelInfo* levels, plas_level_out* trace,
-                          hipStream_t stream);
+// Between reorders: the control step of the reorder that ran on `in` (its
+// energy, the stall test, the schedule) written to `out`, and the grouping
+// table of the next reorder. in and out are two different state buffers.
+hipError_t launch_step(const DevState* in, DevState* out, const LevelInfo* levels, plas_level_out* trace,
+                       int32_t* table, int64_t max_cells, hipStream_t stream);
 // energy_out (device u64) += sum over cells of floor(d(G[p], T[p]) * 2^s).
 hipError_t launch_energy(const float* G, const float* T, int64_t n, int dp, int s,
                          unsigned long long* energy_out, hipStream_t stream);
