@@ -22,6 +22,15 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kRangeBlocks = 256;
+#ifndef PLAS_ASSIGN_MAX_BLOCKS
+#define PLAS_ASSIGN_MAX_BLOCKS 4096
+#endif
+#ifndef PLAS_STAGE_DEPTH
+#define PLAS_STAGE_DEPTH 4
+#endif
+#ifndef PLAS_BLUR_LINES_PER_WAVE
+#define PLAS_BLUR_LINES_PER_WAVE 1
+#endif
 constexpr int kMaxGridBlocks = 4096;
 
 inline int blocks_for(int64_t threads, int64_t cap = kMaxGridBlocks) {
@@ -333,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_blur(const float* __restrict__ in, f
 // the current one is summed. One wave per line, four lines per block.
 constexpr int kStageChunk = 32;
 constexpr int kStageVec = kStageChunk / 4;
-constexpr int kStageDepth = 4;  // chunks whose loads are in flight
+constexpr int kStageDepth = PLAS_STAGE_DEPTH;  // chunks whose loads are in flight
 
 struct StagedRegs {
   float4 enter[kStageVec];
@@ -479,16 +488,10 @@ struct StagedLine {
   }
 };
 
-__global__ __launch_bounds__(kBlock) void k_blur_staged64(const float* __restrict__ in, float* __restrict__ out,
-                                                          int w, const DevState* __restrict__ st, int radius,
-                                                          int vertical, const float* __restrict__ inv) {
-  __shared__ float s_stage[kWavesPerBlock][3][kStageChunk][64];
-  if (st != nullptr && st->done) return;
-  const int r = st != nullptr ? st->r : radius;
-  const int wib = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int64_t line = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wib;
-  if (line >= w) return;  // no block-wide barriers follow
+// One line of a staged blur pass, by one wave.
+__device__ __forceinline__ void blur_staged_line(const float* __restrict__ in, float* __restrict__ out, int w,
+                                                 int r, int vertical, const float* __restrict__ inv,
+                                                 int64_t line, int lane, float (*stage)[kStageChunk][64]) {
   StagedLine L;
   const int64_t base = vertical ? line * 64 : line * w * 64;
   L.src = in + base;
@@ -500,9 +503,9 @@ __global__ __launch_bounds__(kBlock) void k_blur_staged64(const float* __restric
   L.q = lane >> 4;
   L.j = lane & 15;
   L.lane = lane;
-  L.s_enter = s_stage[wib][0];
-  L.s_leave = s_stage[wib][1];
-  L.s_out = s_stage[wib][2];
+  L.s_enter = stage[0];
+  L.s_leave = stage[1];
+  L.s_out = stage[2];
   if (r == 0) {
     for (int x = 0; x < w; ++x) L.dst[x * L.step + lane] = L.src[x * L.step + lane];
     return;
@@ -527,6 +530,21 @@ __global__ __launch_bounds__(kBlock) void k_blur_staged64(const float* __restric
       L.consume(c, ring[b], s);
     }
   }
+}
+
+// One wave per line; a launch of fewer waves than lines walks the lines
+// with a stride.
+__global__ __launch_bounds__(kBlock) void k_blur_staged64(const float* __restrict__ in, float* __restrict__ out,
+                                                          int w, const DevState* __restrict__ st, int radius,
+                                                          int vertical, const float* __restrict__ inv) {
+  __shared__ float s_stage[kWavesPerBlock][3][kStageChunk][64];
+  if (st != nullptr && st->done) return;
+  const int r = st != nullptr ? st->r : radius;
+  const int wib = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  for (int64_t line = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wib; line < w;
+       line += static_cast<int64_t>(gridDim.x) * kWavesPerBlock)
+    blur_staged_line(in, out, w, r, vertical, inv, line, lane, s_stage[wib]);
 }
 
 // ---------------------------------------------------------- group table
@@ -593,27 +611,69 @@ __device__ __forceinline__ uint32_t order_code(int m) {
 //  - the quantised pair costs go to LDS; lane L evaluates orderings
 //    L, L+LG, ... and the lanes pick the first minimum with a butterfly on
 //    (cost, ordering index).
-// Geometry of one reorder's items, read once per thread.
+// Exact quotient a / d for 0 <= a < 2^31 and 1 <= d < 2^30 from a float64
+// reciprocal: the estimate is off by at most one (relative error of the
+// product below 2^-51), and the remainder's sign fixes it.
+struct FastDiv {
+  uint32_t d;
+  double inv;
+  __device__ __forceinline__ void init(uint32_t divisor) {
+    d = divisor;
+    inv = 1.0 / static_cast<double>(divisor);
+  }
+  __device__ __forceinline__ uint32_t div(uint32_t a) const {
+    uint32_t q = static_cast<uint32_t>(static_cast<double>(a) * inv);
+    const int32_t r = static_cast<int32_t>(a - q * d);
+    if (r < 0)
+      --q;
+    else if (r >= static_cast<int32_t>(d))
+      ++q;
+    return q;
+  }
+};
+
+// Geometry of one reorder's items, read once per thread. Item indices, cell
+// indices and counts stay below 2^31 (side <= 46340).
 struct ItemGeometry {
   const int32_t* __restrict__ table;
   int w, beta, nb, dy, dx, R;
-  int64_t gpb, groups, total, strip_rows, strip;
+  uint32_t groups, total, strip_rows, strip;
+  FastDiv by_gpb, by_nb, by_w, by_rest;
+
+  __device__ __forceinline__ void init(const DevState* __restrict__ st, const int32_t* __restrict__ tbl) {
+    table = tbl;
+    w = st->w;
+    beta = st->beta;
+    nb = st->nb;
+    dy = st->dy;
+    dx = st->dx;
+    R = nb * beta;
+    groups = static_cast<uint32_t>(st->groups);
+    total = static_cast<uint32_t>(st->groups + st->singles);
+    strip_rows = static_cast<uint32_t>(w - R) * static_cast<uint32_t>(w);
+    strip = static_cast<uint32_t>(w) * w - static_cast<uint32_t>(R) * R;
+    by_gpb.init(static_cast<uint32_t>(st->groups_per_block > 0 ? st->groups_per_block : 1));
+    by_nb.init(static_cast<uint32_t>(nb));
+    by_w.init(static_cast<uint32_t>(w));
+    by_rest.init(static_cast<uint32_t>(w - R > 0 ? w - R : 1));
+  }
 
   // The four cells of group `item`, or four times the cell of single `item`
   // (cells in no group: first the rolled-grid rows below the nb*beta square,
   // then the columns right of it, then the left-over cell pi(beta^2 - 1) of
   // each block when beta is odd). Inactive items map to cell 0.
-  __device__ __forceinline__ void cells(int64_t item, int32_t cell[4]) const {
+  __device__ __forceinline__ void cells(uint32_t item, int32_t cell[4]) const {
     if (item < groups) {
-      const int64_t b = item / gpb;
-      const int64_t g = item - b * gpb;
-      const int by = static_cast<int>(b / nb);
-      const int bx = static_cast<int>(b - static_cast<int64_t>(by) * nb);
+      const uint32_t b = by_gpb.div(item);
+      const uint32_t g = item - b * by_gpb.d;
+      const int by = static_cast<int>(by_nb.div(b));
+      const int bx = static_cast<int>(b) - by * nb;
+      const int4 t4 = reinterpret_cast<const int4*>(table)[g];
+      const int32_t t[4] = {t4.x, t4.y, t4.z, t4.w};
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int32_t t = table[4 * g + i];
-        int y = dy + by * beta + (t >> 16);
-        int x = dx + bx * beta + (t & 0xffff);
+        int y = dy + by * beta + (t[i] >> 16);
+        int x = dx + bx * beta + (t[i] & 0xffff);
         if (y >= w) y -= w;
         if (x >= w) x -= w;
         cell[i] = y * w + x;
@@ -622,21 +682,23 @@ struct ItemGeometry {
     }
     int32_t p = 0;
     if (item < total) {
-      const int64_t t = item - groups;
+      const uint32_t t = item - groups;
       int u, v;
       if (t < strip) {
         if (t < strip_rows) {
-          u = R + static_cast<int>(t / w);
-          v = static_cast<int>(t % w);
+          const uint32_t qy = by_w.div(t);
+          u = R + static_cast<int>(qy);
+          v = static_cast<int>(t - qy * by_w.d);
         } else {
-          const int64_t t2 = t - strip_rows;
-          u = static_cast<int>(t2 / (w - R));
-          v = R + static_cast<int>(t2 % (w - R));
+          const uint32_t t2 = t - strip_rows;
+          const uint32_t qy = by_rest.div(t2);
+          u = static_cast<int>(qy);
+          v = R + static_cast<int>(t2 - qy * by_rest.d);
         }
       } else {
-        const int64_t b = t - strip;
-        const int by = static_cast<int>(b / nb);
-        const int bx = static_cast<int>(b - static_cast<int64_t>(by) * nb);
+        const uint32_t b = t - strip;
+        const int by = static_cast<int>(by_nb.div(b));
+        const int bx = static_cast<int>(b) - by * nb;
         const int32_t tt = table[static_cast<int64_t>(beta) * beta - 1];
         u = by * beta + (tt >> 16);
         v = bx * beta + (tt & 0xffff);
@@ -650,6 +712,61 @@ struct ItemGeometry {
   }
 };
 
+// Cross-lane moves within 16-lane rows (DPP): the value of lane i ^ (1 << b).
+// Rows are rotated for b = 2 (i + 4 or i - 4 depending on bit 2) and b = 3.
+template <int B>
+__device__ __forceinline__ int dpp_xor(int v) {
+  if constexpr (B == 0) {
+    return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (B == 1) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  } else if constexpr (B == 2) {
+    const int up = __builtin_amdgcn_update_dpp(0, v, 0x12C, 0xF, 0xF, false);    // row_ror 12: lane i + 4
+    const int down = __builtin_amdgcn_update_dpp(0, v, 0x124, 0xF, 0xF, false);  // row_ror 4: lane i - 4
+    return (__lane_id() & 4) ? down : up;
+  } else {
+    return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);  // row_ror 8: lane i ^ 8
+  }
+}
+
+template <int B>
+__device__ __forceinline__ float dpp_xor_f(float v) {
+  return __int_as_float(dpp_xor<B>(__float_as_int(v)));
+}
+
+template <int B>
+__device__ __forceinline__ unsigned long long dpp_xor_u64(unsigned long long v) {
+  const int lo = dpp_xor<B>(static_cast<int>(v & 0xffffffffull));
+  const int hi = dpp_xor<B>(static_cast<int>(v >> 32));
+  return (static_cast<unsigned long long>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+}
+
+// One level of the transposed butterfly over the item's pair partials: lanes
+// with bit B clear keep the even pairs, the others the odd ones, each adding
+// its partner's partial of the kept pair (partner = lane ^ (1 << B)).
+template <int B, int N>
+__device__ __forceinline__ void transpose_level(float* part, bool upper) {
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    const float lo = part[2 * t], hi = part[2 * t + 1];
+    const float sum_lo = lo + dpp_xor_f<B>(lo);
+    const float sum_hi = hi + dpp_xor_f<B>(hi);
+    part[t] = upper ? sum_hi : sum_lo;
+  }
+}
+
+// First minimum across the item's lanes at level B: smaller cost, then
+// smaller ordering index.
+template <int B>
+__device__ __forceinline__ void argmin_level(unsigned long long& best, int& best_m) {
+  const unsigned long long oc = dpp_xor_u64<B>(best);
+  const int om = dpp_xor<B>(best_m);
+  if (oc < best || (oc == best && om < best_m)) {
+    best = oc;
+    best_m = om;
+  }
+}
+
 template <int DP>
 __global__ __launch_bounds__(kBlock) void k_assign(float* __restrict__ G, const float* __restrict__ T,
                                                    int32_t* __restrict__ P,
@@ -662,18 +779,7 @@ __global__ __launch_bounds__(kBlock) void k_assign(float* __restrict__ G, const 
   constexpr int KEEP = 16 / LG;  // pair distances held per lane after the reduction
   __shared__ unsigned long long s_q[kWavesPerBlock][IPW][16];
   ItemGeometry geo;
-  geo.table = table;
-  geo.w = st->w;
-  geo.beta = st->beta;
-  geo.nb = st->nb;
-  geo.dy = st->dy;
-  geo.dx = st->dx;
-  geo.R = geo.nb * geo.beta;
-  geo.gpb = st->groups_per_block;
-  geo.groups = st->groups;
-  geo.total = geo.groups + st->singles;
-  geo.strip_rows = static_cast<int64_t>(geo.w - geo.R) * geo.w;
-  geo.strip = static_cast<int64_t>(geo.w) * geo.w - static_cast<int64_t>(geo.R) * geo.R;
+  geo.init(st, table);
   const double scale = ldexp(1.0, st->s);
   const int lane = threadIdx.x & 63;
   const int wib = threadIdx.x >> 6;
@@ -689,8 +795,8 @@ __global__ __launch_bounds__(kBlock) void k_assign(float* __restrict__ G, const 
   // Software pipeline: the next item's cells (table reads) are resolved
   // while the current item's grid and target cells are in flight.
   int64_t first = wave * IPW;
-  int32_t cell[4];  // cell indices are below 2^31 (side <= 46340)
-  geo.cells(first + slot, cell);
+  int32_t cell[4];
+  geo.cells(static_cast<uint32_t>(first + slot), cell);
   for (; first < geo.total; first += nwaves * IPW) {
     const int64_t item = first + slot;
     const bool active = item < geo.total;
@@ -707,7 +813,10 @@ __global__ __launch_bounds__(kBlock) void k_assign(float* __restrict__ G, const 
       for (int i = 0; i < 4; ++i) old_perm[i] = P[cell[i]];
     }
     int32_t next_cell[4];
-    geo.cells(first + nwaves * IPW + slot, next_cell);
+    {
+      const int64_t next = first + nwaves * IPW + slot;
+      geo.cells(next < geo.total ? static_cast<uint32_t>(next) : geo.total, next_cell);
+    }
 
     // Pair q = 4i + j: grid cell i against target cell j.
     float part[16];
@@ -715,17 +824,10 @@ __global__ __launch_bounds__(kBlock) void k_assign(float* __restrict__ G, const 
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) part[4 * i + j] = chunk_sq(g[i], tg[j]);
-#pragma unroll
-    for (int b = 0; b < LEVELS; ++b) {
-      const bool upper = (sub >> b) & 1;
-#pragma unroll
-      for (int t = 0; t < (8 >> b); ++t) {
-        const float lo = part[2 * t], hi = part[2 * t + 1];
-        const float keep = upper ? hi : lo;
-        const float give = upper ? lo : hi;
-        part[t] = keep + __shfl_xor(give, 1 << b);
-      }
-    }
+    if constexpr (LEVELS > 0) transpose_level<0, 8>(part, sub & 1);
+    if constexpr (LEVELS > 1) transpose_level<1, 4>(part, sub & 2);
+    if constexpr (LEVELS > 2) transpose_level<2, 2>(part, sub & 4);
+    if constexpr (LEVELS > 3) transpose_level<3, 1>(part, sub & 8);
 #pragma unroll
     for (int t = 0; t < KEEP; ++t)
       q_item[t * LG + sub] = static_cast<unsigned long long>(static_cast<double>(part[t]) * scale);
@@ -748,15 +850,10 @@ __global__ __launch_bounds__(kBlock) void k_assign(float* __restrict__ G, const 
       }
     }
     // First minimum across the item's lanes: smaller cost, then smaller index.
-#pragma unroll
-    for (int b = 0; b < LEVELS; ++b) {
-      const unsigned long long oc = __shfl_xor(best, 1 << b);
-      const int om = __shfl_xor(best_m, 1 << b);
-      if (oc < best || (oc == best && om < best_m)) {
-        best = oc;
-        best_m = om;
-      }
-    }
+    if constexpr (LEVELS > 0) argmin_level<0>(best, best_m);
+    if constexpr (LEVELS > 1) argmin_level<1>(best, best_m);
+    if constexpr (LEVELS > 2) argmin_level<2>(best, best_m);
+    if constexpr (LEVELS > 3) argmin_level<3>(best, best_m);
     const unsigned long long self_cost = q_item[0];
     wave_lds_sync();
 
@@ -779,12 +876,24 @@ __global__ __launch_bounds__(kBlock) void k_assign(float* __restrict__ G, const 
 #pragma unroll
     for (int i = 0; i < 4; ++i) cell[i] = next_cell[i];
   }
+  // One pair of atomics per block: waves reduce, then the block.
+  __shared__ unsigned long long s_sum[2][kWavesPerBlock];
   e_acc = wave_sum_u64(e_acc);
   m_acc = wave_sum_u64(m_acc);
   if (lane == 0) {
-    const int slot_acc = static_cast<int>(wave % kAccSlots);
-    atomicAdd(&st->energy_acc[slot_acc], e_acc);
-    atomicAdd(&st->moved_acc[slot_acc], m_acc);
+    s_sum[0][wib] = e_acc;
+    s_sum[1][wib] = m_acc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long e = 0, m = 0;
+    for (int i = 0; i < kWavesPerBlock; ++i) {
+      e += s_sum[0][i];
+      m += s_sum[1][i];
+    }
+    const int slot_acc = static_cast<int>(blockIdx.x % kAccSlots);
+    atomicAdd(&st->energy_acc[slot_acc], e);
+    atomicAdd(&st->moved_acc[slot_acc], m);
   }
 }
 
@@ -973,7 +1082,8 @@ hipError_t launch_gather(const float* X, const int32_t* P, float* G, int64_t n, 
 hipError_t launch_blur_pass(const float* in, float* out, int w, int dp, const DevState* st,
                             int radius, int vertical, const float* inv, hipStream_t stream) {
   if (dp == 64) {
-    const int blocks = (w + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int lines_per_block = kWavesPerBlock * PLAS_BLUR_LINES_PER_WAVE;
+    const int blocks = (w + lines_per_block - 1) / lines_per_block;
     k_blur_staged64<<<blocks, kBlock, 0, stream>>>(in, out, w, st, radius, vertical, inv);
     return hipGetLastError();
   }
@@ -995,7 +1105,7 @@ hipError_t launch_assign(float* G, const float* T, int32_t* P, const int32_t* ta
                          DevState* st, int dp, int64_t max_items, hipStream_t stream) {
   const int64_t items_per_wave = 64 / (dp / 4);
   const int64_t waves = (max_items + items_per_wave - 1) / items_per_wave;
-  const int blocks = blocks_for(waves * 64);
+  const int blocks = blocks_for(waves * 64, PLAS_ASSIGN_MAX_BLOCKS);
   PLAS_DISPATCH_DP(dp, (k_assign<DPV><<<blocks, kBlock, 0, stream>>>(G, T, P, table, st)));
   return hipGetLastError();
 }
