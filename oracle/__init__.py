@@ -42,6 +42,7 @@ class _Params(ctypes.Structure):
         ("start_radius", ctypes.c_double),
         ("max_reorders", ctypes.c_int64),
         ("init_perm", ctypes.c_void_p),
+        ("storage_bf16", ctypes.c_int32),
     ]
 
 
@@ -94,6 +95,13 @@ def lib() -> ctypes.CDLL:
                                                       ctypes.c_int32, i32p,
                                                       ctypes.POINTER(ctypes.c_double)]),
             "plas_ref_blur": (ctypes.c_int32, [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+            "plas_ref_blur_storage": (ctypes.c_int32, [vp, vp, ctypes.c_int32, ctypes.c_int32,
+                                                       ctypes.c_int32, ctypes.c_int32]),
+            "plas_ref_round_bf16": (ctypes.c_float, [ctypes.c_float]),
+            "plas_ref_grid_energy_storage": (ctypes.c_int32, [vp, vp, ctypes.c_int64, ctypes.c_int32,
+                                                              ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                              ctypes.c_int32, u64p, i32p,
+                                                              ctypes.POINTER(ctypes.c_double)]),
             "plas_ref_distance": (ctypes.c_float, [vp, vp, ctypes.c_int32]),
             "plas_ref_quantise": (ctypes.c_uint64, [ctypes.c_float, ctypes.c_int32]),
             "plas_ref_energy_fixed": (ctypes.c_uint64, [vp, vp, ctypes.c_int64, ctypes.c_int32,
@@ -185,16 +193,23 @@ def scale_shift(F: np.ndarray, layout: str = "cn") -> tuple[int, int, float]:
     return int(st), s.value, dmax.value
 
 
-def blur(G: np.ndarray, side: int, r: int) -> np.ndarray:
+def blur(G: np.ndarray, side: int, r: int, storage_bf16: bool = False) -> np.ndarray:
     """G is [N][d] (cell-major); returns T [N][d]."""
     G = _f32(G)
     N, d = G.shape
     assert N == side * side
     T = np.empty_like(G)
-    st = lib().plas_ref_blur(_ptr(G), _ptr(T), side, d, r)
+    st = lib().plas_ref_blur_storage(_ptr(G), _ptr(T), side, d, r, 1 if storage_bf16 else 0)
     if st != OK:
         raise ValueError(f"plas_ref_blur failed: {st}")
     return T
+
+
+def round_bf16(x) -> np.ndarray:
+    """Elementwise round-to-nearest-even to bfloat16, as float32."""
+    a = np.asarray(x, dtype=np.float32)
+    f = lib().plas_ref_round_bf16
+    return np.array([f(float(v)) for v in a.ravel()], dtype=np.float32).reshape(a.shape)
 
 
 def distance(a, b) -> np.float32:
@@ -283,12 +298,13 @@ class SortResult:
 def sort(F: np.ndarray, side: int, seed: int, layout: str = "cn", *, radius_decay: float = 0.95,
          inv_threshold: int = 10000, min_block: int = 16, start_radius: float = 0.0,
          max_reorders: int = 0, init_perm: np.ndarray | None = None,
-         energy_cap: int = 0) -> SortResult:
+         energy_cap: int = 0, storage_bf16: bool = False) -> SortResult:
     F = _f32(F)
     n, d = _nd(F, layout)
     ip = None if init_perm is None else np.ascontiguousarray(init_perm, dtype=np.int32)
     prm = _Params(seed & 0xFFFFFFFFFFFFFFFF, radius_decay, inv_threshold, min_block,
-                  start_radius, max_reorders, None if ip is None else ip.ctypes.data)
+                  start_radius, max_reorders, None if ip is None else ip.ctypes.data,
+                  1 if storage_bf16 else 0)
     cap = 4096
     trace = (_Level * cap)()
     energies = np.zeros(max(energy_cap, 1), dtype=np.uint64)
@@ -316,14 +332,15 @@ def sort(F: np.ndarray, side: int, seed: int, layout: str = "cn", *, radius_deca
 
 
 def grid_energy(F: np.ndarray, perm: np.ndarray | None, side: int, r: int,
-                layout: str = "cn") -> tuple[int, int, int, float]:
+                layout: str = "cn", storage_bf16: bool = False) -> tuple[int, int, int, float]:
     """Returns (status, E, s, mean)."""
     F = _f32(F)
     n, d = _nd(F, layout)
     p = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
     E, s, mean = ctypes.c_uint64(), ctypes.c_int32(), ctypes.c_double()
-    st = lib().plas_ref_grid_energy(_ptr(F), _ptr(p), n, d, side, LAYOUTS[layout], r,
-                                    ctypes.byref(E), ctypes.byref(s), ctypes.byref(mean))
+    st = lib().plas_ref_grid_energy_storage(_ptr(F), _ptr(p), n, d, side, LAYOUTS[layout], r,
+                                            1 if storage_bf16 else 0, ctypes.byref(E),
+                                            ctypes.byref(s), ctypes.byref(mean))
     return int(st), int(E.value), s.value, mean.value
 
 

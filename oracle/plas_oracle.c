@@ -250,6 +250,24 @@ int32_t plas_ref_scale_shift(const float* F, int64_t n, int32_t d, int32_t layou
 /* a float64 brute-force mean within the rounding bound, grid symmetries.    */
 /* ------------------------------------------------------------------------ */
 
+/* Round to bfloat16 (8 exponent bits, 7 stored mantissa bits) to nearest,
+ * ties to even: add half an ulp of the kept part, plus one if the kept part
+ * is odd, then drop the low 16 bits. Infinities and NaNs pass unchanged.
+ * Pinned against torch's float32 -> bfloat16 conversion. */
+float plas_ref_round_bf16(float x)
+{
+    uint32_t u;
+    memcpy(&u, &x, sizeof(u));
+    if ((u & 0x7f800000u) == 0x7f800000u)
+        return x;
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    u &= 0xffff0000u;
+    float y;
+    memcpy(&y, &u, sizeof(y));
+    return y;
+}
+
 static int32_t window_count(int32_t x, int32_t r, int32_t w)
 {
     int32_t lo = x - r < 0 ? 0 : x - r;
@@ -257,8 +275,15 @@ static int32_t window_count(int32_t x, int32_t r, int32_t w)
     return hi - lo + 1;
 }
 
+/* The window mean as stored: float32, or rounded to bfloat16 (the inputs of
+ * a bfloat16 grid are already bfloat16 values; sums stay float32). */
+static float stored(float v, int32_t bf16)
+{
+    return bf16 ? plas_ref_round_bf16(v) : v;
+}
+
 static void box_line(const float* in, ptrdiff_t step, float* out, int32_t w, int32_t r,
-                     const float* inv)
+                     const float* inv, int32_t bf16)
 {
     if (r == 0) {
         for (int32_t x = 0; x < w; x++)
@@ -269,17 +294,23 @@ static void box_line(const float* in, ptrdiff_t step, float* out, int32_t w, int
     float s = in[0];
     for (int32_t t = 1; t <= first_hi; t++)
         s = s + in[t * step];
-    out[0] = s * inv[window_count(0, r, w)];
+    out[0] = stored(s * inv[window_count(0, r, w)], bf16);
     for (int32_t x = 1; x < w; x++) {
         if (x + r <= w - 1)
             s = s + in[(ptrdiff_t)(x + r) * step];
         if (x - r - 1 >= 0)
             s = s - in[(ptrdiff_t)(x - r - 1) * step];
-        out[x * step] = s * inv[window_count(x, r, w)];
+        out[x * step] = stored(s * inv[window_count(x, r, w)], bf16);
     }
 }
 
 int32_t plas_ref_blur(const float* G, float* T, int32_t w, int32_t d, int32_t r)
+{
+    return plas_ref_blur_storage(G, T, w, d, r, 0);
+}
+
+int32_t plas_ref_blur_storage(const float* G, float* T, int32_t w, int32_t d, int32_t r,
+                              int32_t storage_bf16)
 {
     if (G == NULL || T == NULL || w < 1 || d < 1 || r < 0)
         return PLAS_REF_INVALID;
@@ -298,12 +329,14 @@ int32_t plas_ref_blur(const float* G, float* T, int32_t w, int32_t d, int32_t r)
 #pragma omp parallel for schedule(static) if (N >= PAR_MIN_ITEMS)
     for (int32_t y = 0; y < w; y++)
         for (int32_t c = 0; c < d; c++)
-            box_line(G + (int64_t)y * w * d + c, d, H + (int64_t)y * w * d + c, w, r, inv);
+            box_line(G + (int64_t)y * w * d + c, d, H + (int64_t)y * w * d + c, w, r, inv,
+                     storage_bf16);
     /* Vertical pass on the result: every column, every channel. */
 #pragma omp parallel for schedule(static) if (N >= PAR_MIN_ITEMS)
     for (int32_t x = 0; x < w; x++)
         for (int32_t c = 0; c < d; c++)
-            box_line(H + (int64_t)x * d + c, (ptrdiff_t)w * d, T + (int64_t)x * d + c, w, r, inv);
+            box_line(H + (int64_t)x * d + c, (ptrdiff_t)w * d, T + (int64_t)x * d + c, w, r, inv,
+                     storage_bf16);
     free(H);
     free(inv);
     return PLAS_REF_OK;
@@ -572,12 +605,25 @@ int32_t plas_ref_sort(const float* F, int64_t n, int32_t d, int32_t side, int32_
         return PLAS_REF_INVALID;
     const int32_t w = side;
     const int64_t N = n;
+    const int32_t bf16 = prm->storage_bf16 != 0;
+    /* bfloat16 storage: the sort sees the features rounded to bfloat16. */
+    float* rounded = NULL;
+    if (bf16) {
+        rounded = (float*)malloc(sizeof(float) * (size_t)(n * d));
+        if (rounded == NULL)
+            return PLAS_REF_INVALID;
+        for (int64_t i = 0; i < n * d; i++)
+            rounded[i] = plas_ref_round_bf16(F[i]);
+        F = rounded;
+    }
     int32_t s = 0;
     int32_t st = plas_ref_scale_shift(F, n, d, layout, &s, NULL);
-    if (st != PLAS_REF_OK)
+    if (st == PLAS_REF_OK && prm->init_perm && !is_bijection(prm->init_perm, N))
+        st = PLAS_REF_INVALID;
+    if (st != PLAS_REF_OK) {
+        free(rounded);
         return st;
-    if (prm->init_perm && !is_bijection(prm->init_perm, N))
-        return PLAS_REF_INVALID;
+    }
 
     int32_t* P = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
     float* G = (float*)malloc(sizeof(float) * (size_t)(N * d));
@@ -586,6 +632,7 @@ int32_t plas_ref_sort(const float* F, int64_t n, int32_t d, int32_t side, int32_
         free(P);
         free(G);
         free(T);
+        free(rounded);
         return PLAS_REF_INVALID;
     }
     /* Start: random positions (Sec. 3.1) or the caller's arrangement. */
@@ -627,7 +674,7 @@ int32_t plas_ref_sort(const float* F, int64_t n, int32_t d, int32_t side, int32_
                 stop = 1;
                 break;
             }
-            plas_ref_blur(G, T, w, d, r);
+            plas_ref_blur_storage(G, T, w, d, r, bf16);
             uint64_t rk[4];
             plas_ref_draw(prm->seed, 1, (uint64_t)k, rk);
             uint64_t moved = 0;
@@ -678,6 +725,7 @@ int32_t plas_ref_sort(const float* F, int64_t n, int32_t d, int32_t side, int32_
     free(P);
     free(G);
     free(T);
+    free(rounded);
     return PLAS_REF_OK;
 }
 
@@ -689,22 +737,40 @@ int32_t plas_ref_grid_energy(const float* F, const int32_t* perm, int64_t n, int
                              int32_t side, int32_t layout, int32_t r, uint64_t* energy,
                              int32_t* s_out, double* energy_mean)
 {
+    return plas_ref_grid_energy_storage(F, perm, n, d, side, layout, r, 0, energy, s_out,
+                                        energy_mean);
+}
+
+int32_t plas_ref_grid_energy_storage(const float* F, const int32_t* perm, int64_t n, int32_t d,
+                                     int32_t side, int32_t layout, int32_t r, int32_t storage_bf16,
+                                     uint64_t* energy, int32_t* s_out, double* energy_mean)
+{
     if (F == NULL || side < 1 || n != (int64_t)side * side || d < 1 || d > PLAS_REF_MAX_D ||
         r < 0 || (layout != PLAS_REF_LAYOUT_CN && layout != PLAS_REF_LAYOUT_NC))
         return PLAS_REF_INVALID;
     if (perm && !is_bijection(perm, n))
         return PLAS_REF_INVALID;
+    float* rounded = NULL;
+    if (storage_bf16) {
+        rounded = (float*)malloc(sizeof(float) * (size_t)(n * d));
+        for (int64_t i = 0; i < n * d; i++)
+            rounded[i] = plas_ref_round_bf16(F[i]);
+        F = rounded;
+    }
     int32_t s = 0;
     int32_t st = plas_ref_scale_shift(F, n, d, layout, &s, NULL);
-    if (st != PLAS_REF_OK)
+    if (st != PLAS_REF_OK) {
+        free(rounded);
         return st;
+    }
     float* G = (float*)malloc(sizeof(float) * (size_t)(n * d));
     float* T = (float*)malloc(sizeof(float) * (size_t)(n * d));
     plas_ref_gather(F, perm, n, d, layout, G);
-    plas_ref_blur(G, T, side, d, r);
+    plas_ref_blur_storage(G, T, side, d, r, storage_bf16 != 0);
     uint64_t E = plas_ref_energy_fixed(G, T, n, d, s);
     free(G);
     free(T);
+    free(rounded);
     if (energy)
         *energy = E;
     if (s_out)

@@ -44,6 +44,7 @@ typedef struct {
     double start_radius;      /* <= 0: w/2 - 1 (Sec. 3.1) */
     int64_t max_reorders;     /* 0: run to the end of the schedule */
     const int32_t* init_perm; /* NULL: random start (Sec. 3.1) */
+    int32_t storage_bf16;     /* nonzero: features and blurred grids held in bfloat16 */
 } plas_ref_params;
 
 typedef struct {
@@ -85,6 +86,11 @@ int32_t plas_ref_scale_shift(const float* F, int64_t n, int32_t d, int32_t layou
                              int32_t* s_out, double* dmax_out);
 /* Separable box blur with clamped windows: T = V_r(H_r(G)), G and T [N][d]. */
 int32_t plas_ref_blur(const float* G, float* T, int32_t w, int32_t d, int32_t r);
+/* The same, with each pass's output rounded to bfloat16 when storage_bf16. */
+int32_t plas_ref_blur_storage(const float* G, float* T, int32_t w, int32_t d, int32_t r,
+                              int32_t storage_bf16);
+/* x rounded to the nearest bfloat16 (ties to even), returned as float. */
+float plas_ref_round_bf16(float x);
 /* Squared L2 distance, pairwise tree over channels padded to a power of two. */
 float plas_ref_distance(const float* a, const float* b, int32_t d);
 /* floor(dist * 2^s) as an exact unsigned integer. */
@@ -112,6 +118,10 @@ int32_t plas_ref_sort(const float* F, int64_t n, int32_t d, int32_t side, int32_
 int32_t plas_ref_grid_energy(const float* F, const int32_t* perm, int64_t n, int32_t d,
                              int32_t side, int32_t layout, int32_t r, uint64_t* energy,
                              int32_t* s_out, double* energy_mean);
+/* The same with bfloat16 storage of the features and the blurred grid. */
+int32_t plas_ref_grid_energy_storage(const float* F, const int32_t* perm, int64_t n, int32_t d,
+                                     int32_t side, int32_t layout, int32_t r, int32_t storage_bf16,
+                                     uint64_t* energy, int32_t* s_out, double* energy_mean);
 /* The same energy in float64 with direct window means and no quantisation:
  * mean over cells of the squared distance to the blurred grid. */
 double plas_ref_grid_energy_f64(const float* F, const int32_t* perm, int64_t n, int32_t d,
