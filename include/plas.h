@@ -50,11 +50,18 @@ extern "C" {
 #define PLAS_LAYOUT_CN 0 /* channel-major: features[c * n + i] */
 #define PLAS_LAYOUT_NC 1 /* vector-major:  features[i * d + c] */
 
-/* Feature element types. */
+/* Feature element types (of the caller's features array). */
 #define PLAS_DTYPE_F32 0
-#define PLAS_DTYPE_BF16 1 /* not built yet: PLAS_ERR_UNSUPPORTED */
+#define PLAS_DTYPE_BF16 1 /* bfloat16 as uint16 bit patterns */
 
-/* Largest channel count d of the float32 path. */
+/* Storage of the working grids. Arithmetic is float32 either way; with
+ * PLAS_STORAGE_BF16 the features are rounded to bfloat16 (nearest, ties to
+ * even) on entry and every blurred grid is rounded when stored, which halves
+ * the bytes each reorder moves. */
+#define PLAS_STORAGE_F32 0
+#define PLAS_STORAGE_BF16 1
+
+/* Largest channel count d. */
 #define PLAS_MAX_CHANNELS 64
 
 typedef struct plas_context* plas_handle;
@@ -75,7 +82,7 @@ typedef struct {
     int32_t min_block;       /* smallest block side; 16 */
     int32_t profile;         /* nonzero: time the blur and assignment kernels with HIP events (fills *_ms in stats) */
     int32_t reorders_per_sync; /* reorders queued between checks of the device's done flag; 0: library default */
-    int32_t reserved;
+    int32_t storage;         /* PLAS_STORAGE_F32 (default) or PLAS_STORAGE_BF16 */
 } plas_sort_params;
 
 /* One radius level of a finished sort. */
@@ -128,8 +135,8 @@ int32_t plas_set_stream(plas_handle h, void* stream);
  * channels (1 <= d <= PLAS_MAX_CHANNELS) in `layout`, element type `dtype`;
  * read only. perm_out: device int32[n], written in gather form. stats: host
  * memory or NULL. The call returns when the sort has finished on the device.
- * Deterministic: the same inputs and seed give the same permutation, equal
- * bit for bit to the CPU oracle's.
+ * Deterministic: the same inputs, seed and storage give the same permutation,
+ * equal bit for bit to the CPU oracle's for that storage.
  */
 int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int32_t side,
                   int32_t layout, int32_t dtype, const plas_sort_params* params,
@@ -140,12 +147,13 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
  * minimises): arranged = features[perm] (perm: device int32[n] in gather
  * form, or NULL for the identity), target = box blur of half-width `radius`
  * (>= 0), energy = sum over cells of floor(d(arranged[p], target[p]) * 2^s),
- * with s derived from the features' per-channel ranges. Host outputs may be
- * NULL. energy_mean = energy * 2^-s / n.
+ * with s derived from the (stored) features' per-channel ranges, grids held
+ * in `storage`. Host outputs may be NULL. energy_mean = energy * 2^-s / n.
  */
 int32_t plas_grid_energy(plas_handle h, const void* features, const int32_t* perm, int64_t n,
-                         int32_t d, int32_t side, int32_t layout, int32_t dtype, int32_t radius,
-                         uint64_t* energy_fixed, int32_t* scale_shift, double* energy_mean);
+                         int32_t d, int32_t side, int32_t layout, int32_t dtype, int32_t storage,
+                         int32_t radius, uint64_t* energy_fixed, int32_t* scale_shift,
+                         double* energy_mean);
 
 /* A static string naming a status code. */
 const char* plas_status_string(int32_t status);

@@ -3,12 +3,13 @@
  * each kernel can be driven and checked on its own, plus the library's
  * host-side helpers (random draws, schedule, energy scale).
  *
- * Working layout of a grid: device float32 [n][dp], n = side^2, cell-major,
- * dp a power of two in {4, 8, 16, 32, 64} (channels padded with zeros; the
- * library uses dp = max(4, next power of two >= d)). Pointers called device
- * pointers are caller-owned device memory of the handle's device. Status
- * codes and threading rules are those of plas.h. Every call returns after
- * its work has finished on the handle's stream.
+ * Working layout of a grid: device [n][dp], n = side^2, cell-major, dp a
+ * power of two in {4, 8, 16, 32, 64} (channels padded with zeros; the
+ * library uses dp = max(4, next power of two >= d)), elements float32
+ * (storage PLAS_STORAGE_F32) or bfloat16 bit patterns (PLAS_STORAGE_BF16).
+ * Pointers called device pointers are caller-owned device memory of the
+ * handle's device. Status codes and threading rules are those of plas.h.
+ * Every call returns after its work has finished on the handle's stream.
  */
 #ifndef PLAS_STAGES_H
 #define PLAS_STAGES_H
@@ -26,10 +27,10 @@ extern "C" {
  * `radius` (>= 0), rows then columns; each window is clipped to the grid and
  * the sum is taken as a sliding sum along the line (add the entering value,
  * then subtract the leaving one) times float32(1/count). radius 0 copies.
- * grid, target: device float32 [n][dp]; they must not overlap.
+ * grid, target: device [n][dp] grids in `storage`; they must not overlap.
  */
-int32_t plas_stage_blur(plas_handle h, const float* grid, float* target, int32_t side,
-                        int32_t dp, int32_t radius);
+int32_t plas_stage_blur(plas_handle h, const void* grid, void* target, int32_t side, int32_t dp,
+                        int32_t storage, int32_t radius);
 
 /*
  * The shared grouping of one reorder (Sec. 3.1, "Blockwise Linear
@@ -47,21 +48,21 @@ int32_t plas_stage_group_table(plas_handle h, int32_t beta, const uint64_t round
  * every block holds the block-local cells pi(4g..4g+3); each group moves its
  * four cells by the permutation of least integer cost
  * sum_i floor(d(grid[c_i], target[c_sigma(i)]) * 2^scale_shift) (first in
- * lexicographic order on ties). grid (device float32 [n][dp]) and perm
+ * lexicographic order on ties). grid (device [n][dp] in `storage`) and perm
  * (device int32[n]) are updated in place; target is read only. energy (host,
  * may be NULL) receives the integer energy of the new arrangement against
  * target over all cells; moved (host, may be NULL) the cells that moved.
  * 2 <= beta <= side, 0 <= dy, dx < side.
  */
-int32_t plas_stage_assign(plas_handle h, float* grid, const float* target, int32_t* perm,
-                          int32_t side, int32_t dp, int32_t beta, int32_t dy, int32_t dx,
-                          const uint64_t round_keys[4], int32_t scale_shift, uint64_t* energy,
-                          uint64_t* moved);
+int32_t plas_stage_assign(plas_handle h, void* grid, const void* target, int32_t* perm,
+                          int32_t side, int32_t dp, int32_t storage, int32_t beta, int32_t dy,
+                          int32_t dx, const uint64_t round_keys[4], int32_t scale_shift,
+                          uint64_t* energy, uint64_t* moved);
 
 /* Integer energy of grid against target: sum over cells of
- * floor(d(grid[p], target[p]) * 2^scale_shift). Both device [n][dp]. */
-int32_t plas_stage_energy(plas_handle h, const float* grid, const float* target, int32_t side,
-                          int32_t dp, int32_t scale_shift, uint64_t* energy);
+ * floor(d(grid[p], target[p]) * 2^scale_shift). Both device [n][dp] in `storage`. */
+int32_t plas_stage_energy(plas_handle h, const void* grid, const void* target, int32_t side,
+                          int32_t dp, int32_t storage, int32_t scale_shift, uint64_t* energy);
 
 /* out[i] = pi(i) for i < n, pi the keyed bijection of [0, n) (the random
  * start arrangement of Sec. 3.1 uses the keys of draw (seed, 0, 0)).

@@ -31,6 +31,9 @@ LAYOUT_CN = 0
 LAYOUT_NC = 1
 DTYPE_F32 = 0
 DTYPE_BF16 = 1
+STORAGE_F32 = 0
+STORAGE_BF16 = 1
+STORAGES = {"f32": STORAGE_F32, "bf16": STORAGE_BF16}
 MAX_CHANNELS = 64
 
 # Every symbol declared in include/plas.h and include/plas_stages.h.
@@ -61,7 +64,7 @@ class SortParams(ctypes.Structure):
         ("min_block", ctypes.c_int32),
         ("profile", ctypes.c_int32),
         ("reorders_per_sync", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("storage", ctypes.c_int32),
     ]
 
 
@@ -119,14 +122,14 @@ def library() -> ctypes.CDLL:
         "plas_set_stream": (i32, [vp, vp]),
         "plas_sort": (i32, [vp, vp, i64, i32, i32, i32, i32, ctypes.POINTER(SortParams), vp,
                             ctypes.POINTER(SortStats)]),
-        "plas_grid_energy": (i32, [vp, vp, vp, i64, i32, i32, i32, i32, i32, u64p, i32p,
+        "plas_grid_energy": (i32, [vp, vp, vp, i64, i32, i32, i32, i32, i32, i32, u64p, i32p,
                                    ctypes.POINTER(ctypes.c_double)]),
         "plas_status_string": (ctypes.c_char_p, [i32]),
         "plas_last_error": (ctypes.c_char_p, [vp]),
-        "plas_stage_blur": (i32, [vp, vp, vp, i32, i32, i32]),
+        "plas_stage_blur": (i32, [vp, vp, vp, i32, i32, i32, i32]),
         "plas_stage_group_table": (i32, [vp, i32, u64p, vp]),
-        "plas_stage_assign": (i32, [vp, vp, vp, vp, i32, i32, i32, i32, i32, u64p, i32, u64p, u64p]),
-        "plas_stage_energy": (i32, [vp, vp, vp, i32, i32, i32, u64p]),
+        "plas_stage_assign": (i32, [vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, u64p, i32, u64p, u64p]),
+        "plas_stage_energy": (i32, [vp, vp, vp, i32, i32, i32, i32, u64p]),
         "plas_stage_bijection": (i32, [vp, i64, u64p, vp]),
         "plas_philox4x64_10": (None, [u64p, u64p, u64p]),
         "plas_draw": (None, [u64, u64, u64, u64p]),
@@ -238,12 +241,14 @@ class Context:
     def sort(self, features, side: int | None = None, seed: int = 0x5EED, layout: str = "cn", *,
              radius_decay: float = 0.95, inv_threshold: int = 10000, min_block: int = 16,
              start_radius: float = 0.0, max_reorders: int = 0, init_perm=None,
-             profile: bool = False, reorders_per_sync: int = 0, out=None):
+             profile: bool = False, reorders_per_sync: int = 0, storage: str = "f32", out=None):
         """Sort device features ([d][n] for layout "cn", [n][d] for "nc",
-        float32, contiguous) onto a side x side grid. Returns (perm, stats):
-        perm is an int32 device tensor in gather form, stats a SortResult."""
+        float32 or bfloat16, contiguous) onto a side x side grid, with the
+        working grids stored as float32 ("f32") or bfloat16 ("bf16"). Returns
+        (perm, stats): perm is an int32 device tensor in gather form, stats a
+        SortResult."""
         import torch
-        _check_tensor(features, torch.float32)
+        dtype = _feature_dtype(features)
         if layout == "cn":
             d, n = features.shape
             lay = LAYOUT_CN
@@ -267,6 +272,7 @@ class Context:
         prm.max_reorders = max_reorders
         prm.profile = 1 if profile else 0
         prm.reorders_per_sync = reorders_per_sync
+        prm.storage = STORAGES[storage]
         if init_perm is not None:
             _check_tensor(init_perm, torch.int32)
             prm.init_perm = init_perm.data_ptr()
@@ -278,7 +284,7 @@ class Context:
         stats.trace_cap = cap
         self._bind_stream()
         st = library().plas_sort(self._h, ctypes.c_void_p(features.data_ptr()), n, d, side, lay,
-                                 DTYPE_F32, ctypes.byref(prm), ctypes.c_void_p(out.data_ptr()),
+                                 dtype, ctypes.byref(prm), ctypes.c_void_p(out.data_ptr()),
                                  ctypes.byref(stats))
         self._check(st, "plas_sort")
         res = SortResult(
@@ -293,10 +299,10 @@ class Context:
         return out, res
 
     def grid_energy(self, features, perm=None, side: int | None = None, radius: int = 1,
-                    layout: str = "cn"):
+                    layout: str = "cn", storage: str = "f32"):
         """(energy_fixed, scale_shift, energy_mean) of features[perm] at radius."""
         import torch
-        _check_tensor(features, torch.float32)
+        dtype = _feature_dtype(features)
         if layout == "cn":
             d, n = features.shape
             lay = LAYOUT_CN
@@ -312,23 +318,24 @@ class Context:
         E, s, mean = ctypes.c_uint64(), ctypes.c_int32(), ctypes.c_double()
         self._bind_stream()
         st = library().plas_grid_energy(self._h, ctypes.c_void_p(features.data_ptr()), p, n, d, side,
-                                        lay, DTYPE_F32, radius, ctypes.byref(E), ctypes.byref(s),
-                                        ctypes.byref(mean))
+                                        lay, dtype, STORAGES[storage], radius, ctypes.byref(E),
+                                        ctypes.byref(s), ctypes.byref(mean))
         self._check(st, "plas_grid_energy")
         return int(E.value), s.value, mean.value
 
     # ---- stages (working layout [n][dp] float32)
 
     def stage_blur(self, grid, side: int, radius: int, target=None):
+        """grid: device [n][dp] float32 or bfloat16 (the storage)."""
         import torch
-        _check_tensor(grid, torch.float32)
+        storage = _grid_storage(grid)
         dp = grid.shape[1]
         if target is None:
             target = torch.empty_like(grid)
         self._bind_stream()
         self._check(library().plas_stage_blur(self._h, ctypes.c_void_p(grid.data_ptr()),
-                                              ctypes.c_void_p(target.data_ptr()), side, dp, radius),
-                    "plas_stage_blur")
+                                              ctypes.c_void_p(target.data_ptr()), side, dp, storage,
+                                              radius), "plas_stage_blur")
         return target
 
     def stage_group_table(self, beta: int, round_keys):
@@ -344,26 +351,27 @@ class Context:
                      scale_shift: int):
         """One reorder in place on grid ([n][dp]) and perm. Returns (energy, moved)."""
         import torch
-        _check_tensor(grid, torch.float32)
-        _check_tensor(target, torch.float32)
+        storage = _grid_storage(grid)
+        if target.dtype != grid.dtype:
+            raise ValueError("grid and target must have the same storage")
         _check_tensor(perm, torch.int32)
         E, M = ctypes.c_uint64(), ctypes.c_uint64()
         self._bind_stream()
         self._check(library().plas_stage_assign(
             self._h, ctypes.c_void_p(grid.data_ptr()), ctypes.c_void_p(target.data_ptr()),
-            ctypes.c_void_p(perm.data_ptr()), side, grid.shape[1], beta, dy, dx, _u64x4(round_keys),
-            scale_shift, ctypes.byref(E), ctypes.byref(M)), "plas_stage_assign")
+            ctypes.c_void_p(perm.data_ptr()), side, grid.shape[1], storage, beta, dy, dx,
+            _u64x4(round_keys), scale_shift, ctypes.byref(E), ctypes.byref(M)), "plas_stage_assign")
         return int(E.value), int(M.value)
 
     def stage_energy(self, grid, target, side: int, scale_shift: int) -> int:
-        import torch
-        _check_tensor(grid, torch.float32)
-        _check_tensor(target, torch.float32)
+        storage = _grid_storage(grid)
+        if target.dtype != grid.dtype:
+            raise ValueError("grid and target must have the same storage")
         E = ctypes.c_uint64()
         self._bind_stream()
         self._check(library().plas_stage_energy(self._h, ctypes.c_void_p(grid.data_ptr()),
                                                 ctypes.c_void_p(target.data_ptr()), side,
-                                                grid.shape[1], scale_shift, ctypes.byref(E)),
+                                                grid.shape[1], storage, scale_shift, ctypes.byref(E)),
                     "plas_stage_energy")
         return int(E.value)
 
@@ -390,6 +398,28 @@ class SortResult:
     assign_ms: float = 0.0
     assign_launches: int = 0
     total_ms: float = 0.0
+
+
+def _feature_dtype(t) -> int:
+    import torch
+    if t.dtype == torch.float32:
+        _check_tensor(t, torch.float32)
+        return DTYPE_F32
+    if t.dtype == torch.bfloat16:
+        _check_tensor(t, torch.bfloat16)
+        return DTYPE_BF16
+    raise ValueError(f"features must be float32 or bfloat16, got {t.dtype}")
+
+
+def _grid_storage(t) -> int:
+    import torch
+    if t.dtype == torch.float32:
+        _check_tensor(t, torch.float32)
+        return STORAGE_F32
+    if t.dtype == torch.bfloat16:
+        _check_tensor(t, torch.bfloat16)
+        return STORAGE_BF16
+    raise ValueError(f"grids are float32 or bfloat16, got {t.dtype}")
 
 
 def _check_tensor(t, dtype):

@@ -49,7 +49,7 @@ struct plas_context {
   hipStream_t stream = nullptr;
   std::string error;
   // Device workspace, grown on demand and kept.
-  DeviceBuffer grid_g, grid_h, grid_t;  // [n][dp] float32 each
+  DeviceBuffer grid_g, grid_h, grid_t;  // [n][dp] each, float32 or bfloat16
   DeviceBuffer perm;                    // int32[n]
   DeviceBuffer table;                   // int32[beta^2]
   DeviceBuffer inv;                     // float32 1/c, c = 0..w
@@ -134,6 +134,10 @@ T* as(DeviceBuffer& b) {
   return static_cast<T*>(b.ptr);
 }
 
+size_t storage_bytes(int32_t storage) { return storage == PLAS_STORAGE_BF16 ? 2 : 4; }
+
+bool valid_storage(int32_t storage) { return storage == PLAS_STORAGE_F32 || storage == PLAS_STORAGE_BF16; }
+
 int padded_channels(int d) {
   int dp = 4;
   while (dp < d) dp *= 2;
@@ -191,8 +195,7 @@ int32_t check_features(plas_context* h, const void* features, int64_t n, int32_t
     return fail(h, PLAS_ERR_INVALID_ARGUMENT, "n must equal side * side");
   if (d < 1) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "d must be >= 1");
   if (!valid_layout(layout)) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "unknown layout");
-  if (dtype == PLAS_DTYPE_BF16) return fail(h, PLAS_ERR_UNSUPPORTED, "bf16 features are not built yet");
-  if (dtype != PLAS_DTYPE_F32) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "unknown dtype");
+  if (dtype != PLAS_DTYPE_F32 && dtype != PLAS_DTYPE_BF16) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "unknown dtype");
   if (d > PLAS_MAX_CHANNELS)
     return fail(h, PLAS_ERR_UNSUPPORTED, "d above PLAS_MAX_CHANNELS is not supported");
   return PLAS_OK;
@@ -200,17 +203,18 @@ int32_t check_features(plas_context* h, const void* features, int64_t n, int32_t
 
 // Ingest + range + scale shift, leaving X (cell-major padded features) in
 // grid_t. Returns NONFINITE if a value is not finite.
-int32_t prepare_features(plas_context* h, const float* features, int64_t n, int32_t d, int32_t layout,
-                         int dp, int32_t* s_out) {
-  const size_t grid_bytes = static_cast<size_t>(n) * dp * sizeof(float);
+int32_t prepare_features(plas_context* h, const void* features, int32_t dtype, int64_t n, int32_t d,
+                         int32_t layout, int dp, int32_t storage, int32_t* s_out) {
+  const size_t grid_bytes = static_cast<size_t>(n) * dp * storage_bytes(storage);
   PLAS_HIP(h, reserve(h->grid_g, grid_bytes));
   PLAS_HIP(h, reserve(h->grid_h, grid_bytes));
   PLAS_HIP(h, reserve(h->grid_t, grid_bytes));
   PLAS_HIP(h, reserve(h->range_part, plas::range_partial_floats(dp) * sizeof(float)));
   PLAS_HIP(h, reserve(h->range_out, (2 * 64 + 1) * sizeof(float)));
-  float* X = as<float>(h->grid_t);
-  PLAS_HIP(h, plas::launch_ingest(features, n, d, layout, dp, X, h->stream));
-  PLAS_HIP(h, plas::launch_range(X, n, d, dp, as<float>(h->range_part), as<float>(h->range_out), h->stream));
+  void* X = h->grid_t.ptr;
+  PLAS_HIP(h, plas::launch_ingest(features, dtype == PLAS_DTYPE_BF16, n, d, layout, dp, storage, X, h->stream));
+  PLAS_HIP(h, plas::launch_range(X, n, d, dp, storage, as<float>(h->range_part), as<float>(h->range_out),
+                                 h->stream));
   PLAS_HIP(h, hipMemcpyAsync(h->range_host, h->range_out.ptr, (2 * dp + 1) * sizeof(float),
                              hipMemcpyDeviceToHost, h->stream));
   PLAS_HIP(h, hipStreamSynchronize(h->stream));
@@ -220,7 +224,8 @@ int32_t prepare_features(plas_context* h, const float* features, int64_t n, int3
   return PLAS_OK;
 }
 
-// Validate a caller permutation (device int32[n]); uses grid_h as scratch.
+// Validate a caller permutation (device int32[n]); uses grid_h as scratch
+// (at least n * 4 * 2 bytes in either storage).
 int32_t check_permutation(plas_context* h, const int32_t* perm, int64_t n) {
   int32_t* counts = as<int32_t>(h->grid_h);
   int32_t* flag = reinterpret_cast<int32_t*>(as<unsigned long long>(h->scratch) + 8);
@@ -286,6 +291,7 @@ int32_t plas_sort_params_init(plas_sort_params* p) {
   p->min_block = 16;
   p->profile = 0;
   p->reorders_per_sync = 0;
+  p->storage = PLAS_STORAGE_F32;
   return PLAS_OK;
 }
 
@@ -376,6 +382,7 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
   if (prm.inv_threshold < 1) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "inv_threshold must be >= 1");
   if (prm.min_block < 1) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "min_block must be >= 1");
   if (prm.max_reorders < 0) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "max_reorders must be >= 0");
+  if (!valid_storage(prm.storage)) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "unknown storage");
   if (stats != nullptr && stats->struct_size != sizeof(plas_sort_stats))
     return fail(h, PLAS_ERR_INVALID_ARGUMENT, "stats->struct_size does not match this library");
 
@@ -395,7 +402,8 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
 
   // Workspace.
   int32_t s = 0;
-  st = prepare_features(h, static_cast<const float*>(features), n, d, layout, dp, &s);
+  const int32_t storage = prm.storage;
+  st = prepare_features(h, features, dtype, n, d, layout, dp, storage, &s);
   if (st != PLAS_OK) return st;
   PLAS_HIP(h, reserve(h->perm, static_cast<size_t>(n) * sizeof(int32_t)));
   PLAS_HIP(h, reserve(h->table, static_cast<size_t>(max_cells) * sizeof(int32_t)));
@@ -407,9 +415,9 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
                              hipMemcpyHostToDevice, h->stream));
   PLAS_HIP(h, hipMemsetAsync(h->trace.ptr, 0, levels.size() * sizeof(plas_level_out), h->stream));
 
-  float* G = as<float>(h->grid_g);
-  float* H = as<float>(h->grid_h);
-  float* T = as<float>(h->grid_t);  // holds X until the gather
+  void* G = h->grid_g.ptr;
+  void* H = h->grid_h.ptr;
+  void* T = h->grid_t.ptr;  // holds X until the gather
   int32_t* P = as<int32_t>(h->perm);
 
   // Start arrangement: the caller's, or the keyed bijection of draw
@@ -423,7 +431,7 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
     const plas::Words4 k0 = plas::draw(prm.seed, plas::kDrawStart, 0);
     PLAS_HIP(h, plas::launch_start_perm(P, n, k0.v, h->stream));
   }
-  PLAS_HIP(h, plas::launch_gather(T, P, G, n, dp, h->stream));
+  PLAS_HIP(h, plas::launch_gather(T, P, G, n, dp, storage, h->stream));
 
   // First reorder's state.
   DevState* S = h->state_host;
@@ -466,11 +474,11 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
       PLAS_HIP(h, plas::launch_step(&states[cur], Sd, Ld, Td, table, max_cells, h->stream));
       cur ^= 1;
       if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 0], h->stream));
-      PLAS_HIP(h, plas::launch_blur_pass(G, H, w, dp, Sd, 0, 0, as<float>(h->inv), h->stream));
-      PLAS_HIP(h, plas::launch_blur_pass(H, T, w, dp, Sd, 0, 1, as<float>(h->inv), h->stream));
+      PLAS_HIP(h, plas::launch_blur_pass(G, H, w, dp, storage, Sd, 0, 0, as<float>(h->inv), h->stream));
+      PLAS_HIP(h, plas::launch_blur_pass(H, T, w, dp, storage, Sd, 0, 1, as<float>(h->inv), h->stream));
       if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 1], h->stream));
       if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 2], h->stream));
-      PLAS_HIP(h, plas::launch_assign(G, T, P, table, Sd, dp, max_items, h->stream));
+      PLAS_HIP(h, plas::launch_assign(G, T, P, table, Sd, dp, storage, max_items, h->stream));
       if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 3], h->stream));
     }
     const int64_t first_slot = slots;
@@ -536,17 +544,18 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
 }
 
 int32_t plas_grid_energy(plas_handle h, const void* features, const int32_t* perm, int64_t n, int32_t d,
-                         int32_t side, int32_t layout, int32_t dtype, int32_t radius, uint64_t* energy_fixed,
-                         int32_t* scale_shift_out, double* energy_mean) {
+                         int32_t side, int32_t layout, int32_t dtype, int32_t storage, int32_t radius,
+                         uint64_t* energy_fixed, int32_t* scale_shift_out, double* energy_mean) {
   int32_t st = check_features(h, features, n, d, side, layout, dtype);
   if (st != PLAS_OK) return st;
   h->error.clear();
   if (radius < 0) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "radius must be >= 0");
+  if (!valid_storage(storage)) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "unknown storage");
   DeviceScope scope(h->device);
   if (!scope.ok()) return fail(h, PLAS_ERR_HIP, "hipSetDevice failed");
   const int dp = padded_channels(d);
   int32_t s = 0;
-  st = prepare_features(h, static_cast<const float*>(features), n, d, layout, dp, &s);
+  st = prepare_features(h, features, dtype, n, d, layout, dp, storage, &s);
   if (st != PLAS_OK) return st;
   if (perm != nullptr) {
     st = check_permutation(h, perm, n);
@@ -554,15 +563,15 @@ int32_t plas_grid_energy(plas_handle h, const void* features, const int32_t* per
   }
   st = upload_inverse_counts(h, side);
   if (st != PLAS_OK) return st;
-  float* G = as<float>(h->grid_g);
-  float* H = as<float>(h->grid_h);
-  float* T = as<float>(h->grid_t);
-  PLAS_HIP(h, plas::launch_gather(T, perm, G, n, dp, h->stream));
-  PLAS_HIP(h, plas::launch_blur_pass(G, H, side, dp, nullptr, radius, 0, as<float>(h->inv), h->stream));
-  PLAS_HIP(h, plas::launch_blur_pass(H, T, side, dp, nullptr, radius, 1, as<float>(h->inv), h->stream));
+  void* G = h->grid_g.ptr;
+  void* H = h->grid_h.ptr;
+  void* T = h->grid_t.ptr;
+  PLAS_HIP(h, plas::launch_gather(T, perm, G, n, dp, storage, h->stream));
+  PLAS_HIP(h, plas::launch_blur_pass(G, H, side, dp, storage, nullptr, radius, 0, as<float>(h->inv), h->stream));
+  PLAS_HIP(h, plas::launch_blur_pass(H, T, side, dp, storage, nullptr, radius, 1, as<float>(h->inv), h->stream));
   unsigned long long* acc = as<unsigned long long>(h->scratch);
   PLAS_HIP(h, hipMemsetAsync(acc, 0, sizeof(unsigned long long), h->stream));
-  PLAS_HIP(h, plas::launch_energy(G, T, n, dp, s, acc, h->stream));
+  PLAS_HIP(h, plas::launch_energy(G, T, n, dp, storage, s, acc, h->stream));
   PLAS_HIP(h, hipMemcpyAsync(h->u64_host, acc, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
   PLAS_HIP(h, hipStreamSynchronize(h->stream));
   const uint64_t E = h->u64_host[0];
@@ -576,19 +585,21 @@ int32_t plas_grid_energy(plas_handle h, const void* features, const int32_t* per
 
 static bool valid_dp(int32_t dp) { return dp == 4 || dp == 8 || dp == 16 || dp == 32 || dp == 64; }
 
-int32_t plas_stage_blur(plas_handle h, const float* grid, float* target, int32_t side, int32_t dp,
+int32_t plas_stage_blur(plas_handle h, const void* grid, void* target, int32_t side, int32_t dp, int32_t storage,
                         int32_t radius) {
   if (h == nullptr) return PLAS_ERR_INVALID_ARGUMENT;
-  if (grid == nullptr || target == nullptr || side < 1 || side > 46340 || !valid_dp(dp) || radius < 0)
+  if (grid == nullptr || target == nullptr || side < 1 || side > 46340 || !valid_dp(dp) || radius < 0 ||
+      !valid_storage(storage))
     return fail(h, PLAS_ERR_INVALID_ARGUMENT, "bad blur arguments");
   DeviceScope scope(h->device);
   const int64_t n = static_cast<int64_t>(side) * side;
-  PLAS_HIP(h, reserve(h->grid_h, static_cast<size_t>(n) * dp * sizeof(float)));
+  PLAS_HIP(h, reserve(h->grid_h, static_cast<size_t>(n) * dp * storage_bytes(storage)));
   int32_t st = upload_inverse_counts(h, side);
   if (st != PLAS_OK) return st;
-  float* H = as<float>(h->grid_h);
-  PLAS_HIP(h, plas::launch_blur_pass(grid, H, side, dp, nullptr, radius, 0, as<float>(h->inv), h->stream));
-  PLAS_HIP(h, plas::launch_blur_pass(H, target, side, dp, nullptr, radius, 1, as<float>(h->inv), h->stream));
+  void* H = h->grid_h.ptr;
+  PLAS_HIP(h, plas::launch_blur_pass(grid, H, side, dp, storage, nullptr, radius, 0, as<float>(h->inv), h->stream));
+  PLAS_HIP(h, plas::launch_blur_pass(H, target, side, dp, storage, nullptr, radius, 1, as<float>(h->inv),
+                                     h->stream));
   PLAS_HIP(h, hipStreamSynchronize(h->stream));
   return PLAS_OK;
 }
@@ -632,13 +643,14 @@ int32_t plas_stage_group_table(plas_handle h, int32_t beta, const uint64_t round
   return PLAS_OK;
 }
 
-int32_t plas_stage_assign(plas_handle h, float* grid, const float* target, int32_t* perm, int32_t side,
-                          int32_t dp, int32_t beta, int32_t dy, int32_t dx, const uint64_t round_keys[4],
-                          int32_t scale_shift_in, uint64_t* energy, uint64_t* moved) {
+int32_t plas_stage_assign(plas_handle h, void* grid, const void* target, int32_t* perm, int32_t side,
+                          int32_t dp, int32_t storage, int32_t beta, int32_t dy, int32_t dx,
+                          const uint64_t round_keys[4], int32_t scale_shift_in, uint64_t* energy,
+                          uint64_t* moved) {
   if (h == nullptr) return PLAS_ERR_INVALID_ARGUMENT;
   if (grid == nullptr || target == nullptr || perm == nullptr || round_keys == nullptr || side < 2 ||
-      side > 46340 || !valid_dp(dp) || beta < 2 || beta > side || dy < 0 || dy >= side || dx < 0 ||
-      dx >= side)
+      side > 46340 || !valid_dp(dp) || !valid_storage(storage) || beta < 2 || beta > side || dy < 0 ||
+      dy >= side || dx < 0 || dx >= side)
     return fail(h, PLAS_ERR_INVALID_ARGUMENT, "bad assign arguments");
   DeviceScope scope(h->device);
   const int64_t cells = static_cast<int64_t>(beta) * beta;
@@ -648,7 +660,7 @@ int32_t plas_stage_assign(plas_handle h, float* grid, const float* target, int32
   DevState* Sd = as<DevState>(h->stage_state);
   PLAS_HIP(h, plas::launch_group_table(as<int32_t>(h->table), Sd, cells, h->stream));
   const int64_t items = h->state_host->groups + h->state_host->singles;
-  PLAS_HIP(h, plas::launch_assign(grid, target, perm, as<int32_t>(h->table), Sd, dp, items, h->stream));
+  PLAS_HIP(h, plas::launch_assign(grid, target, perm, as<int32_t>(h->table), Sd, dp, storage, items, h->stream));
   PLAS_HIP(h, hipMemcpyAsync(h->state_host, Sd, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
   PLAS_HIP(h, hipStreamSynchronize(h->stream));
   unsigned long long E = 0, M = 0;
@@ -661,15 +673,15 @@ int32_t plas_stage_assign(plas_handle h, float* grid, const float* target, int32
   return PLAS_OK;
 }
 
-int32_t plas_stage_energy(plas_handle h, const float* grid, const float* target, int32_t side, int32_t dp,
-                          int32_t scale_shift_in, uint64_t* energy) {
+int32_t plas_stage_energy(plas_handle h, const void* grid, const void* target, int32_t side, int32_t dp,
+                          int32_t storage, int32_t scale_shift_in, uint64_t* energy) {
   if (h == nullptr) return PLAS_ERR_INVALID_ARGUMENT;
-  if (grid == nullptr || target == nullptr || side < 1 || side > 46340 || !valid_dp(dp))
+  if (grid == nullptr || target == nullptr || side < 1 || side > 46340 || !valid_dp(dp) || !valid_storage(storage))
     return fail(h, PLAS_ERR_INVALID_ARGUMENT, "bad energy arguments");
   DeviceScope scope(h->device);
   unsigned long long* acc = as<unsigned long long>(h->scratch);
   PLAS_HIP(h, hipMemsetAsync(acc, 0, sizeof(unsigned long long), h->stream));
-  PLAS_HIP(h, plas::launch_energy(grid, target, static_cast<int64_t>(side) * side, dp, scale_shift_in, acc,
+  PLAS_HIP(h, plas::launch_energy(grid, target, static_cast<int64_t>(side) * side, dp, storage, scale_shift_in, acc,
                                   h->stream));
   PLAS_HIP(h, hipMemcpyAsync(h->u64_host, acc, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
   PLAS_HIP(h, hipStreamSynchronize(h->stream));

@@ -2,10 +2,14 @@
 // 2312.13299): ingest, range, start arrangement, gather, separable box blur,
 // grouping table, blockwise assignment with its energy, and the controller.
 //
-// Working layout: a grid is float32 [n][DP], cell-major, DP a power of two
-// (4..64) with zero padding beyond the d real channels. A cell of DP = 64 is
-// 256 bytes, two full 128-byte cache lines, so the assignment kernel's random
-// cell reads waste nothing, and a blur line is read as whole cells.
+// Working layout: a grid is [n][DP], cell-major, DP a power of two (4..64)
+// with zero padding beyond the d real channels, stored as float32 or as
+// bfloat16 (S = float or S = uint16_t holding bfloat16 bits). A cell of
+// DP = 64 is 256 bytes in float32 (two 128-byte lines) or 128 bytes in
+// bfloat16 (one line), so the assignment kernel's random cell reads waste
+// nothing, and a blur line is read as whole cells. All arithmetic is float32:
+// bfloat16 values widen exactly, and results are rounded to bfloat16 (nearest,
+// ties to even) only when they are stored.
 //
 // Floating point: compiled without contraction (-ffp-contract=off) and with
 // denormals kept, so every float operation below is one IEEE-rounded add,
@@ -40,38 +44,73 @@ inline int blocks_for(int64_t threads, int64_t cap = kMaxGridBlocks) {
   return static_cast<int>(b);
 }
 
+// ---------------------------------------------------------------- storage
+
+// bfloat16 is the high half of a float32: widening is exact.
+__device__ __forceinline__ float bf16_to_float(uint32_t bits) { return __uint_as_float(bits << 16); }
+
+// Nearest bfloat16, ties to even: add 0x7fff plus the kept part's lowest bit,
+// keep the high half. Infinities and NaNs keep their high half.
+__device__ __forceinline__ uint32_t float_to_bf16(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return u >> 16;
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+template <typename S>
+struct Storage;
+
+template <>
+struct Storage<float> {
+  using Quad = float4;  // four channels
+  __device__ static __forceinline__ float widen(float v) { return v; }
+  __device__ static __forceinline__ float narrow(float v) { return v; }
+  __device__ static __forceinline__ float4 widen4(float4 q) { return q; }
+};
+
+template <>
+struct Storage<uint16_t> {
+  using Quad = uint2;  // four channels
+  __device__ static __forceinline__ float widen(uint16_t v) { return bf16_to_float(v); }
+  __device__ static __forceinline__ uint16_t narrow(float v) { return static_cast<uint16_t>(float_to_bf16(v)); }
+  __device__ static __forceinline__ float4 widen4(uint2 q) {
+    return make_float4(bf16_to_float(q.x & 0xffffu), bf16_to_float(q.x >> 16), bf16_to_float(q.y & 0xffffu),
+                       bf16_to_float(q.y >> 16));
+  }
+};
+
 // ----------------------------------------------------------------- ingest
 
 // Channel-major [d][n] -> [n][DP]: a 64-cell tile goes through LDS so that
 // both the reads (64 consecutive cells of one channel) and the writes
 // (64 consecutive cells of DP channels) are contiguous.
-template <int DP>
-__global__ __launch_bounds__(kBlock) void k_ingest_cn(const float* __restrict__ F, int64_t n, int d,
-                                                      float* __restrict__ X) {
+template <int DP, typename SI, typename SO>
+__global__ __launch_bounds__(kBlock) void k_ingest_cn(const SI* __restrict__ F, int64_t n, int d,
+                                                      SO* __restrict__ X) {
   __shared__ float tile[DP][65];
   const int64_t n0 = static_cast<int64_t>(blockIdx.x) * 64;
   for (int e = threadIdx.x; e < DP * 64; e += kBlock) {
     const int c = e >> 6, i = e & 63;
     const int64_t cell = n0 + i;
-    tile[c][i] = (c < d && cell < n) ? F[static_cast<int64_t>(c) * n + cell] : 0.0f;
+    tile[c][i] = (c < d && cell < n) ? Storage<SI>::widen(F[static_cast<int64_t>(c) * n + cell]) : 0.0f;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < DP * 64; e += kBlock) {
     const int i = e / DP, c = e % DP;
     const int64_t cell = n0 + i;
-    if (cell < n) X[cell * DP + c] = tile[c][i];
+    if (cell < n) X[cell * DP + c] = Storage<SO>::narrow(tile[c][i]);
   }
 }
 
-template <int DP>
-__global__ __launch_bounds__(kBlock) void k_ingest_nc(const float* __restrict__ F, int64_t n, int d,
-                                                      float* __restrict__ X) {
+template <int DP, typename SI, typename SO>
+__global__ __launch_bounds__(kBlock) void k_ingest_nc(const SI* __restrict__ F, int64_t n, int d,
+                                                      SO* __restrict__ X) {
   const int64_t total = n * DP;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   for (int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; e < total; e += stride) {
     const int64_t cell = e / DP;
     const int c = static_cast<int>(e % DP);
-    X[e] = c < d ? F[cell * d + c] : 0.0f;
+    X[e] = Storage<SO>::narrow(c < d ? Storage<SI>::widen(F[cell * d + c]) : 0.0f);
   }
 }
 
@@ -79,8 +118,8 @@ __global__ __launch_bounds__(kBlock) void k_ingest_nc(const float* __restrict__ 
 
 // Each thread owns one channel (the grid stride is a multiple of DP), so a
 // block reduces to DP partial min/max values in LDS.
-template <int DP>
-__global__ __launch_bounds__(kBlock) void k_range_partial(const float* __restrict__ X, int64_t n,
+template <int DP, typename S>
+__global__ __launch_bounds__(kBlock) void k_range_partial(const S* __restrict__ X, int64_t n,
                                                           float* __restrict__ part) {
   __shared__ float s_lo[kBlock], s_hi[kBlock], s_bad[kBlock];
   const int t = threadIdx.x;
@@ -88,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_range_partial(const float* __restric
   const int64_t total = n * DP;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   for (int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + t; e < total; e += stride) {
-    const float v = X[e];
+    const float v = Storage<S>::widen(X[e]);
     if (!__builtin_isfinite(v)) bad = 1.0f;
     lo = fminf(lo, v);
     hi = fmaxf(hi, v);
@@ -170,13 +209,14 @@ __global__ __launch_bounds__(kBlock) void k_verify_counts(const int32_t* __restr
     if (counts[p] != 1) atomicOr(flag, 1);
 }
 
-// G[p] = X[P[p]] (P NULL: identity), 16 bytes per thread.
-template <int DP>
-__global__ __launch_bounds__(kBlock) void k_gather(const float* __restrict__ X, const int32_t* __restrict__ P,
-                                                   float* __restrict__ G, int64_t n) {
+// G[p] = X[P[p]] (P NULL: identity), four channels per thread.
+template <int DP, typename S>
+__global__ __launch_bounds__(kBlock) void k_gather(const S* __restrict__ X, const int32_t* __restrict__ P,
+                                                   S* __restrict__ G, int64_t n) {
   constexpr int LG = DP / 4;
-  const float4* __restrict__ src = reinterpret_cast<const float4*>(X);
-  float4* __restrict__ dst = reinterpret_cast<float4*>(G);
+  using Quad = typename Storage<S>::Quad;
+  const Quad* __restrict__ src = reinterpret_cast<const Quad*>(X);
+  Quad* __restrict__ dst = reinterpret_cast<Quad*>(G);
   const int64_t total = n * LG;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   for (int64_t e = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; e < total; e += stride) {
@@ -214,24 +254,27 @@ __device__ __forceinline__ void wave_lds_sync() {
 // of a wave, so every remaining branch is uniform.
 constexpr int kBlurUnroll = 12;
 
+template <typename S>
 struct BlurLine {
-  const float* __restrict__ src;
-  float* __restrict__ dst;
+  const S* __restrict__ src;
+  S* __restrict__ dst;
   int64_t step;
   const float* __restrict__ inv;
   int w;
   int r;
 
-  __device__ __forceinline__ float load(int t) const { return src[static_cast<int64_t>(t) * step]; }
+  __device__ __forceinline__ float load(int t) const {
+    return Storage<S>::widen(src[static_cast<int64_t>(t) * step]);
+  }
   __device__ __forceinline__ void store(int x, float s) const {
     const int hi = x + r < w - 1 ? x + r : w - 1;
     const int lo = x - r > 0 ? x - r : 0;
-    dst[static_cast<int64_t>(x) * step] = s * inv[hi - lo + 1];
+    dst[static_cast<int64_t>(x) * step] = Storage<S>::narrow(s * inv[hi - lo + 1]);
   }
 };
 
-template <bool ENTER, bool LEAVE>
-__device__ __forceinline__ void blur_fetch(const BlurLine& L, int x0, float* enter, float* leave) {
+template <bool ENTER, bool LEAVE, typename L_t>
+__device__ __forceinline__ void blur_fetch(const L_t& L, int x0, float* enter, float* leave) {
 #pragma unroll
   for (int i = 0; i < kBlurUnroll; ++i) {
     if (ENTER) enter[i] = L.load(x0 + i + L.r);
@@ -239,8 +282,8 @@ __device__ __forceinline__ void blur_fetch(const BlurLine& L, int x0, float* ent
   }
 }
 
-template <bool ENTER, bool LEAVE>
-__device__ __forceinline__ void blur_apply(const BlurLine& L, int x0, const float* enter, const float* leave,
+template <bool ENTER, bool LEAVE, typename L_t>
+__device__ __forceinline__ void blur_apply(const L_t& L, int x0, const float* enter, const float* leave,
                                            float& s) {
 #pragma unroll
   for (int i = 0; i < kBlurUnroll; ++i) {
@@ -251,8 +294,8 @@ __device__ __forceinline__ void blur_apply(const BlurLine& L, int x0, const floa
 }
 
 // Positions [xb, xe) where entering/leaving values exist as ENTER/LEAVE say.
-template <bool ENTER, bool LEAVE>
-__device__ __forceinline__ void blur_range(const BlurLine& L, int xb, int xe, float& s) {
+template <bool ENTER, bool LEAVE, typename L_t>
+__device__ __forceinline__ void blur_range(const L_t& L, int xb, int xe, float& s) {
   const int full = (xe - xb) / kBlurUnroll;
   int x = xb;
   if (full > 0) {
@@ -277,8 +320,8 @@ __device__ __forceinline__ void blur_range(const BlurLine& L, int xb, int xe, fl
   }
 }
 
-template <int DP>
-__global__ __launch_bounds__(kBlock) void k_blur(const float* __restrict__ in, float* __restrict__ out,
+template <int DP, typename S>
+__global__ __launch_bounds__(kBlock) void k_blur(const S* __restrict__ in, S* __restrict__ out,
                                                  int w, const DevState* __restrict__ st, int radius,
                                                  int vertical, const float* __restrict__ inv) {
   if (st != nullptr && st->done) return;
@@ -290,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_blur(const float* __restrict__ in, f
   const int c = lane % DP;
   if (line >= w) return;
   const int64_t base = vertical ? line * DP + c : line * w * DP + c;
-  BlurLine L;
+  BlurLine<S> L;
   L.src = in + base;
   L.dst = out + base;
   L.step = vertical ? static_cast<int64_t>(w) * DP : DP;
@@ -331,28 +374,64 @@ __global__ __launch_bounds__(kBlock) void k_blur(const float* __restrict__ in, f
 
 // Blur pass for 64-channel cells, staged through LDS. Same arithmetic as
 // k_blur (one running sum per line and channel, same operation order), but
-// the memory side is reorganised: a dword load per position can only keep
-// one position of 64 chains in flight per instruction, which caps the bytes
-// in flight far below what HBM needs. Here every lane loads 16 bytes
-// (4 channels) of one of 4 consecutive positions, so one instruction brings
-// 4 positions (1 KB) of the wave's line; kStageChunk positions of the
-// entering and of the leaving stream go through LDS, where lane = channel
-// reads them back in order. Outputs return through LDS and leave as 16-byte
-// stores. The loads of the next kStageDepth - 1 chunks are in flight while
-// the current one is summed. One wave per line, four lines per block.
+// the memory side is reorganised: a per-position load of one channel per lane
+// can only keep one position of 64 chains in flight per instruction, which
+// caps the bytes in flight far below what HBM needs. Here every lane loads
+// 16 bytes (4 float32 or 8 bfloat16 channels) of one of kPos consecutive
+// positions, so one instruction brings 4 (float32) or 8 (bfloat16) positions
+// of the wave's line; kStageChunk positions of the entering and of the
+// leaving stream go through LDS as float32, where lane = channel reads them
+// back in order. Outputs return through LDS and leave as 16-byte stores
+// (rounded to the storage type). The loads of the next kStageDepth - 1
+// chunks are in flight while the current one is summed. One wave per line,
+// four lines per block.
 constexpr int kStageChunk = 32;
-constexpr int kStageVec = kStageChunk / 4;
 constexpr int kStageDepth = PLAS_STAGE_DEPTH;  // chunks whose loads are in flight
 
+template <typename S>
+struct StagedShape {
+  static constexpr int kChannels = 16 / static_cast<int>(sizeof(S));  // channels per 16-byte load
+  static constexpr int kLanesPerCell = 64 / kChannels;
+  static constexpr int kPos = 64 / kLanesPerCell;  // positions per load instruction
+  static constexpr int kVec = kStageChunk / kPos;  // loads per stream per chunk
+};
+
+template <typename S>
 struct StagedRegs {
-  float4 enter[kStageVec];
-  float4 leave[kStageVec];
+  uint4 enter[StagedShape<S>::kVec];
+  uint4 leave[StagedShape<S>::kVec];
   float mult;  // lane p < kStageChunk: float32(1/count) of the chunk's position p
 };
 
+// 16 loaded bytes of one position to float32 channels in LDS, and back.
+__device__ __forceinline__ void stage_in(float* row, const uint4 v, float) {
+  *reinterpret_cast<uint4*>(row) = v;
+}
+__device__ __forceinline__ void stage_in(float* row, const uint4 v, uint16_t) {
+  *reinterpret_cast<float4*>(row) =
+      make_float4(bf16_to_float(v.x & 0xffffu), bf16_to_float(v.x >> 16), bf16_to_float(v.y & 0xffffu),
+                  bf16_to_float(v.y >> 16));
+  *reinterpret_cast<float4*>(row + 4) =
+      make_float4(bf16_to_float(v.z & 0xffffu), bf16_to_float(v.z >> 16), bf16_to_float(v.w & 0xffffu),
+                  bf16_to_float(v.w >> 16));
+}
+__device__ __forceinline__ uint4 stage_out(const float* row, float) {
+  return *reinterpret_cast<const uint4*>(row);
+}
+__device__ __forceinline__ uint4 stage_out(const float* row, uint16_t) {
+  uint4 v;
+  v.x = float_to_bf16(row[0]) | (float_to_bf16(row[1]) << 16);
+  v.y = float_to_bf16(row[2]) | (float_to_bf16(row[3]) << 16);
+  v.z = float_to_bf16(row[4]) | (float_to_bf16(row[5]) << 16);
+  v.w = float_to_bf16(row[6]) | (float_to_bf16(row[7]) << 16);
+  return v;
+}
+
+template <typename S>
 struct StagedLine {
-  const float* __restrict__ src;
-  float* __restrict__ dst;
+  using Shape = StagedShape<S>;
+  const S* __restrict__ src;
+  S* __restrict__ dst;
   const float* __restrict__ inv;
   int64_t step;
   int w, r, first_hi, n_init;
@@ -361,18 +440,18 @@ struct StagedLine {
   float (*s_leave)[64];
   float (*s_out)[64];
 
-  __device__ __forceinline__ float4 ld(int t) const {
-    return reinterpret_cast<const float4*>(src + static_cast<int64_t>(t) * step)[j];
+  __device__ __forceinline__ uint4 ld(int t) const {
+    return reinterpret_cast<const uint4*>(src + static_cast<int64_t>(t) * step)[j];
   }
 
   // Chunks 0 .. n_init-1 cover positions 0 .. first_hi of the starting sum;
   // chunk n_init + k covers output positions 1 + k*kStageChunk onwards.
-  __device__ __forceinline__ void fetch(int c, StagedRegs& R) const {
-    const float4 zero = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  __device__ __forceinline__ void fetch(int c, StagedRegs<S>& R) const {
+    const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
     if (c < n_init) {
 #pragma unroll
-      for (int i = 0; i < kStageVec; ++i) {
-        const int t = c * kStageChunk + 4 * i + q;
+      for (int i = 0; i < Shape::kVec; ++i) {
+        const int t = c * kStageChunk + Shape::kPos * i + q;
         R.enter[i] = t <= first_hi ? ld(t) : zero;
         R.leave[i] = zero;
       }
@@ -380,8 +459,8 @@ struct StagedLine {
     } else {
       const int x0 = 1 + (c - n_init) * kStageChunk;
 #pragma unroll
-      for (int i = 0; i < kStageVec; ++i) {
-        const int x = x0 + 4 * i + q;
+      for (int i = 0; i < Shape::kVec; ++i) {
+        const int x = x0 + Shape::kPos * i + q;
         const int a = x + r, b = x - r - 1;
         R.enter[i] = (x < w && a <= w - 1) ? ld(a) : zero;
         R.leave[i] = (x < w && b >= 0) ? ld(b) : zero;
@@ -435,11 +514,11 @@ struct StagedLine {
   // Lanes exchange the staged values through LDS. DS instructions of one
   // wave execute in issue order, and every LDS read below may alias an
   // earlier LDS write in the compiler's view, so program order suffices.
-  __device__ __forceinline__ void consume(int c, const StagedRegs& R, float& s) const {
+  __device__ __forceinline__ void consume(int c, const StagedRegs<S>& R, float& s) const {
 #pragma unroll
-    for (int i = 0; i < kStageVec; ++i) {
-      *reinterpret_cast<float4*>(&s_enter[4 * i + q][4 * j]) = R.enter[i];
-      *reinterpret_cast<float4*>(&s_leave[4 * i + q][4 * j]) = R.leave[i];
+    for (int i = 0; i < Shape::kVec; ++i) {
+      stage_in(&s_enter[Shape::kPos * i + q][Shape::kChannels * j], R.enter[i], S());
+      stage_in(&s_leave[Shape::kPos * i + q][Shape::kChannels * j], R.leave[i], S());
     }
     if (c < n_init) {
       const int t0 = c * kStageChunk;
@@ -457,7 +536,7 @@ struct StagedLine {
           s = t <= first_hi ? added : s;
         }
       }
-      if (c == n_init - 1) dst[lane] = s * inv[first_hi + 1];
+      if (c == n_init - 1) dst[lane] = Storage<S>::narrow(s * inv[first_hi + 1]);
       return;
     }
     const int x0 = 1 + (c - n_init) * kStageChunk;
@@ -479,20 +558,21 @@ struct StagedLine {
     else
       run_mixed(x0, mult_bits, s);
 #pragma unroll
-    for (int i = 0; i < kStageVec; ++i) {
-      const int x = x0 + 4 * i + q;
+    for (int i = 0; i < Shape::kVec; ++i) {
+      const int x = x0 + Shape::kPos * i + q;
       if (x < w)
-        reinterpret_cast<float4*>(dst + static_cast<int64_t>(x) * step)[j] =
-            *reinterpret_cast<const float4*>(&s_out[4 * i + q][4 * j]);
+        reinterpret_cast<uint4*>(dst + static_cast<int64_t>(x) * step)[j] =
+            stage_out(&s_out[Shape::kPos * i + q][Shape::kChannels * j], S());
     }
   }
 };
 
 // One line of a staged blur pass, by one wave.
-__device__ __forceinline__ void blur_staged_line(const float* __restrict__ in, float* __restrict__ out, int w,
-                                                 int r, int vertical, const float* __restrict__ inv,
-                                                 int64_t line, int lane, float (*stage)[kStageChunk][64]) {
-  StagedLine L;
+template <typename S>
+__device__ __forceinline__ void blur_staged_line(const S* __restrict__ in, S* __restrict__ out, int w, int r,
+                                                 int vertical, const float* __restrict__ inv, int64_t line,
+                                                 int lane, float (*stage)[kStageChunk][64]) {
+  StagedLine<S> L;
   const int64_t base = vertical ? line * 64 : line * w * 64;
   L.src = in + base;
   L.dst = out + base;
@@ -500,8 +580,8 @@ __device__ __forceinline__ void blur_staged_line(const float* __restrict__ in, f
   L.step = vertical ? static_cast<int64_t>(w) * 64 : 64;
   L.w = w;
   L.r = r;
-  L.q = lane >> 4;
-  L.j = lane & 15;
+  L.q = lane / StagedShape<S>::kLanesPerCell;
+  L.j = lane % StagedShape<S>::kLanesPerCell;
   L.lane = lane;
   L.s_enter = stage[0];
   L.s_leave = stage[1];
@@ -516,7 +596,7 @@ __device__ __forceinline__ void blur_staged_line(const float* __restrict__ in, f
   // A ring of kStageDepth register chunks: chunk c + kStageDepth - 1 is
   // requested before chunk c is summed.
   float s = 0.0f;
-  StagedRegs ring[kStageDepth];
+  StagedRegs<S> ring[kStageDepth];
 #pragma unroll
   for (int b = 0; b < kStageDepth - 1; ++b)
     if (b < n_chunks) L.fetch(b, ring[b]);
@@ -534,8 +614,9 @@ __device__ __forceinline__ void blur_staged_line(const float* __restrict__ in, f
 
 // One wave per line; a launch of fewer waves than lines walks the lines
 // with a stride.
-__global__ __launch_bounds__(kBlock) void k_blur_staged64(const float* __restrict__ in, float* __restrict__ out,
-                                                          int w, const DevState* __restrict__ st, int radius,
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_blur_staged64(const S* __restrict__ in, S* __restrict__ out, int w,
+                                                          const DevState* __restrict__ st, int radius,
                                                           int vertical, const float* __restrict__ inv) {
   __shared__ float s_stage[kWavesPerBlock][3][kStageChunk][64];
   if (st != nullptr && st->done) return;
@@ -544,7 +625,7 @@ __global__ __launch_bounds__(kBlock) void k_blur_staged64(const float* __restric
   const int lane = threadIdx.x & 63;
   for (int64_t line = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wib; line < w;
        line += static_cast<int64_t>(gridDim.x) * kWavesPerBlock)
-    blur_staged_line(in, out, w, r, vertical, inv, line, lane, s_stage[wib]);
+    blur_staged_line<S>(in, out, w, r, vertical, inv, line, lane, s_stage[wib]);
 }
 
 // ---------------------------------------------------------- group table
@@ -767,8 +848,8 @@ __device__ __forceinline__ void argmin_level(unsigned long long& best, int& best
   }
 }
 
-template <int DP>
-__global__ __launch_bounds__(kBlock) void k_assign(float* __restrict__ G, const float* __restrict__ T,
+template <int DP, typename S>
+__global__ __launch_bounds__(kBlock) void k_assign(S* __restrict__ G, const S* __restrict__ T,
                                                    int32_t* __restrict__ P,
                                                    const int32_t* __restrict__ table,
                                                    DevState* __restrict__ st) {
@@ -787,9 +868,10 @@ __global__ __launch_bounds__(kBlock) void k_assign(float* __restrict__ G, const 
   unsigned long long* q_item = s_q[wib][slot];
   const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * kBlock) >> 6;
-  const float4* __restrict__ G4 = reinterpret_cast<const float4*>(G);
-  const float4* __restrict__ T4 = reinterpret_cast<const float4*>(T);
-  float4* __restrict__ Gout = reinterpret_cast<float4*>(G);
+  using Quad = typename Storage<S>::Quad;
+  const Quad* __restrict__ G4 = reinterpret_cast<const Quad*>(G);
+  const Quad* __restrict__ T4 = reinterpret_cast<const Quad*>(T);
+  Quad* __restrict__ Gout = reinterpret_cast<Quad*>(G);
   unsigned long long e_acc = 0, m_acc = 0;
 
   // Software pipeline: the next item's cells (table reads) are resolved
@@ -801,7 +883,7 @@ __global__ __launch_bounds__(kBlock) void k_assign(float* __restrict__ G, const 
     const int64_t item = first + slot;
     const bool active = item < geo.total;
     const bool is_group = item < geo.groups;
-    float4 g[4], tg[4];
+    Quad g[4], tg[4];
     int32_t old_perm[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -820,10 +902,18 @@ __global__ __launch_bounds__(kBlock) void k_assign(float* __restrict__ G, const 
 
     // Pair q = 4i + j: grid cell i against target cell j.
     float part[16];
+    {
+      float4 gf[4], tf[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i) {
+        gf[i] = Storage<S>::widen4(g[i]);
+        tf[i] = Storage<S>::widen4(tg[i]);
+      }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) part[4 * i + j] = chunk_sq(g[i], tg[j]);
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) part[4 * i + j] = chunk_sq(gf[i], tf[j]);
+    }
     if constexpr (LEVELS > 0) transpose_level<0, 8>(part, sub & 1);
     if constexpr (LEVELS > 1) transpose_level<1, 4>(part, sub & 2);
     if constexpr (LEVELS > 2) transpose_level<2, 2>(part, sub & 4);
@@ -899,8 +989,8 @@ __global__ __launch_bounds__(kBlock) void k_assign(float* __restrict__ G, const 
 
 // ----------------------------------------------------------------- energy
 
-template <int DP>
-__global__ __launch_bounds__(kBlock) void k_energy(const float* __restrict__ G, const float* __restrict__ T,
+template <int DP, typename S>
+__global__ __launch_bounds__(kBlock) void k_energy(const S* __restrict__ G, const S* __restrict__ T,
                                                    int64_t n, double scale,
                                                    unsigned long long* __restrict__ out) {
   constexpr int LG = DP / 4;
@@ -909,13 +999,14 @@ __global__ __launch_bounds__(kBlock) void k_energy(const float* __restrict__ G, 
   const int sub = lane % LG, slot = lane / LG;
   const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * kBlock) >> 6;
-  const float4* __restrict__ G4 = reinterpret_cast<const float4*>(G);
-  const float4* __restrict__ T4 = reinterpret_cast<const float4*>(T);
+  using Quad = typename Storage<S>::Quad;
+  const Quad* __restrict__ G4 = reinterpret_cast<const Quad*>(G);
+  const Quad* __restrict__ T4 = reinterpret_cast<const Quad*>(T);
   unsigned long long acc = 0;
   for (int64_t first = wave * IPW; first < n; first += nwaves * IPW) {
     const int64_t p = first + slot;
     const int64_t pc = p < n ? p : 0;
-    float v = chunk_sq(G4[pc * LG + sub], T4[pc * LG + sub]);
+    float v = chunk_sq(Storage<S>::widen4(G4[pc * LG + sub]), Storage<S>::widen4(T4[pc * LG + sub]));
 #pragma unroll
     for (int m = 1; m < LG; m <<= 1) v = v + __shfl_xor(v, m);
     if (p < n && sub == 0) acc += static_cast<unsigned long long>(static_cast<double>(v) * scale);
@@ -1037,23 +1128,55 @@ __global__ __launch_bounds__(kBlock) void k_step(const DevState* __restrict__ in
     default: return hipErrorInvalidValue;             \
   }
 
-hipError_t launch_ingest(const float* features, int64_t n, int d, int layout, int dp, float* X,
-                         hipStream_t stream) {
+// The body sees SV = the storage element type (float, or uint16_t holding
+// bfloat16 bits).
+#define PLAS_DISPATCH_STORAGE(storage, ...)                \
+  if ((storage) == kStorageF32) {                          \
+    using SV = float;                                      \
+    __VA_ARGS__;                                           \
+  } else if ((storage) == kStorageBF16) {                  \
+    using SV = uint16_t;                                   \
+    __VA_ARGS__;                                           \
+  } else {                                                 \
+    return hipErrorInvalidValue;                           \
+  }
+
+hipError_t launch_ingest(const void* features, int input_bf16, int64_t n, int d, int layout, int dp, int storage,
+                         void* X, hipStream_t stream) {
   if (layout == 0) {
     const int blocks = static_cast<int>((n + 63) / 64);
-    PLAS_DISPATCH_DP(dp, (k_ingest_cn<DPV><<<blocks, kBlock, 0, stream>>>(features, n, d, X)));
+    PLAS_DISPATCH_STORAGE(storage, {
+      if (input_bf16) {
+        PLAS_DISPATCH_DP(dp, (k_ingest_cn<DPV, uint16_t, SV><<<blocks, kBlock, 0, stream>>>(
+                                 static_cast<const uint16_t*>(features), n, d, static_cast<SV*>(X))));
+      } else {
+        PLAS_DISPATCH_DP(dp, (k_ingest_cn<DPV, float, SV><<<blocks, kBlock, 0, stream>>>(
+                                 static_cast<const float*>(features), n, d, static_cast<SV*>(X))));
+      }
+    });
   } else {
     const int blocks = blocks_for(n * dp, 65536);
-    PLAS_DISPATCH_DP(dp, (k_ingest_nc<DPV><<<blocks, kBlock, 0, stream>>>(features, n, d, X)));
+    PLAS_DISPATCH_STORAGE(storage, {
+      if (input_bf16) {
+        PLAS_DISPATCH_DP(dp, (k_ingest_nc<DPV, uint16_t, SV><<<blocks, kBlock, 0, stream>>>(
+                                 static_cast<const uint16_t*>(features), n, d, static_cast<SV*>(X))));
+      } else {
+        PLAS_DISPATCH_DP(dp, (k_ingest_nc<DPV, float, SV><<<blocks, kBlock, 0, stream>>>(
+                                 static_cast<const float*>(features), n, d, static_cast<SV*>(X))));
+      }
+    });
   }
   return hipGetLastError();
 }
 
 size_t range_partial_floats(int dp) { return static_cast<size_t>(kRangeBlocks) * 3 * dp; }
 
-hipError_t launch_range(const float* X, int64_t n, int d, int dp, float* part, float* out,
+hipError_t launch_range(const void* X, int64_t n, int d, int dp, int storage, float* part, float* out,
                         hipStream_t stream) {
-  PLAS_DISPATCH_DP(dp, (k_range_partial<DPV><<<kRangeBlocks, kBlock, 0, stream>>>(X, n, part)));
+  PLAS_DISPATCH_STORAGE(storage, {
+    PLAS_DISPATCH_DP(dp, (k_range_partial<DPV, SV><<<kRangeBlocks, kBlock, 0, stream>>>(
+                             static_cast<const SV*>(X), n, part)));
+  });
   PLAS_DISPATCH_DP(dp, (k_range_finish<DPV><<<1, 64, 0, stream>>>(part, kRangeBlocks, d, out)));
   return hipGetLastError();
 }
@@ -1072,26 +1195,34 @@ hipError_t launch_check_perm(const int32_t* init, int64_t n, int32_t* counts, in
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const float* X, const int32_t* P, float* G, int64_t n, int dp,
+hipError_t launch_gather(const void* X, const int32_t* P, void* G, int64_t n, int dp, int storage,
                          hipStream_t stream) {
   const int blocks = blocks_for(n * (dp / 4), 65536);
-  PLAS_DISPATCH_DP(dp, (k_gather<DPV><<<blocks, kBlock, 0, stream>>>(X, P, G, n)));
+  PLAS_DISPATCH_STORAGE(storage, {
+    PLAS_DISPATCH_DP(dp, (k_gather<DPV, SV><<<blocks, kBlock, 0, stream>>>(static_cast<const SV*>(X), P,
+                                                                          static_cast<SV*>(G), n)));
+  });
   return hipGetLastError();
 }
 
-hipError_t launch_blur_pass(const float* in, float* out, int w, int dp, const DevState* st,
+hipError_t launch_blur_pass(const void* in, void* out, int w, int dp, int storage, const DevState* st,
                             int radius, int vertical, const float* inv, hipStream_t stream) {
   if (dp == 64) {
     const int lines_per_block = kWavesPerBlock * PLAS_BLUR_LINES_PER_WAVE;
     const int blocks = (w + lines_per_block - 1) / lines_per_block;
-    k_blur_staged64<<<blocks, kBlock, 0, stream>>>(in, out, w, st, radius, vertical, inv);
+    PLAS_DISPATCH_STORAGE(storage, {
+      k_blur_staged64<SV><<<blocks, kBlock, 0, stream>>>(static_cast<const SV*>(in), static_cast<SV*>(out), w,
+                                                         st, radius, vertical, inv);
+    });
     return hipGetLastError();
   }
   const int lines_per_wave = 64 / dp;
   const int64_t waves = (w + lines_per_wave - 1) / lines_per_wave;
   const int blocks = static_cast<int>((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-  PLAS_DISPATCH_DP(dp, (k_blur<DPV><<<blocks, kBlock, 0, stream>>>(in, out, w, st, radius,
-                                                                    vertical, inv)));
+  PLAS_DISPATCH_STORAGE(storage, {
+    PLAS_DISPATCH_DP(dp, (k_blur<DPV, SV><<<blocks, kBlock, 0, stream>>>(
+                             static_cast<const SV*>(in), static_cast<SV*>(out), w, st, radius, vertical, inv)));
+  });
   return hipGetLastError();
 }
 
@@ -1101,12 +1232,15 @@ hipError_t launch_group_table(int32_t* table, const DevState* st, int64_t max_ce
   return hipGetLastError();
 }
 
-hipError_t launch_assign(float* G, const float* T, int32_t* P, const int32_t* table,
-                         DevState* st, int dp, int64_t max_items, hipStream_t stream) {
+hipError_t launch_assign(void* G, const void* T, int32_t* P, const int32_t* table, DevState* st, int dp,
+                         int storage, int64_t max_items, hipStream_t stream) {
   const int64_t items_per_wave = 64 / (dp / 4);
   const int64_t waves = (max_items + items_per_wave - 1) / items_per_wave;
   const int blocks = blocks_for(waves * 64, PLAS_ASSIGN_MAX_BLOCKS);
-  PLAS_DISPATCH_DP(dp, (k_assign<DPV><<<blocks, kBlock, 0, stream>>>(G, T, P, table, st)));
+  PLAS_DISPATCH_STORAGE(storage, {
+    PLAS_DISPATCH_DP(dp, (k_assign<DPV, SV><<<blocks, kBlock, 0, stream>>>(
+                             static_cast<SV*>(G), static_cast<const SV*>(T), P, table, st)));
+  });
   return hipGetLastError();
 }
 
@@ -1116,16 +1250,20 @@ hipError_t launch_step(const DevState* in, DevState* out, const LevelInfo* level
   return hipGetLastError();
 }
 
-hipError_t launch_energy(const float* G, const float* T, int64_t n, int dp, int s,
+hipError_t launch_energy(const void* G, const void* T, int64_t n, int dp, int storage, int s,
                          unsigned long long* energy_out, hipStream_t stream) {
   const int64_t items_per_wave = 64 / (dp / 4);
   const int64_t waves = (n + items_per_wave - 1) / items_per_wave;
   const int blocks = blocks_for(waves * 64);
   const double scale = ldexp(1.0, s);
-  PLAS_DISPATCH_DP(dp, (k_energy<DPV><<<blocks, kBlock, 0, stream>>>(G, T, n, scale, energy_out)));
+  PLAS_DISPATCH_STORAGE(storage, {
+    PLAS_DISPATCH_DP(dp, (k_energy<DPV, SV><<<blocks, kBlock, 0, stream>>>(
+                             static_cast<const SV*>(G), static_cast<const SV*>(T), n, scale, energy_out)));
+  });
   return hipGetLastError();
 }
 
+#undef PLAS_DISPATCH_STORAGE
 #undef PLAS_DISPATCH_DP
 
 }  // namespace plas

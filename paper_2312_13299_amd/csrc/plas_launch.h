@@ -19,14 +19,19 @@ struct plas_level_out {  // same layout as plas_level_stat in plas.h
   uint64_t moved;
 };
 
-// features (layout CN [d][n] or NC [n][d]) -> X [n][dp], channels >= d zero.
-hipError_t launch_ingest(const float* features, int64_t n, int d, int layout, int dp, float* X,
-                         hipStream_t stream);
+// Storage of the working grids.
+constexpr int kStorageF32 = 0;
+constexpr int kStorageBF16 = 1;
+
+// features (layout CN [d][n] or NC [n][d]; float32, or bfloat16 bits if
+// input_bf16) -> X [n][dp] in `storage`, channels >= d zero.
+hipError_t launch_ingest(const void* features, int input_bf16, int64_t n, int d, int layout, int dp, int storage,
+                         void* X, hipStream_t stream);
 // Per-channel min/max of X[n][dp] over the first d channels, and a flag set
 // if any value is NaN or infinite. out: [dp] mins, [dp] maxs, then the flag
-// (as a float slot holding 0 or 1). part: scratch of range_partials_floats().
+// (as a float slot holding 0 or 1). part: scratch of range_partial_floats().
 size_t range_partial_floats(int dp);
-hipError_t launch_range(const float* X, int64_t n, int d, int dp, float* part, float* out,
+hipError_t launch_range(const void* X, int64_t n, int d, int dp, int storage, float* part, float* out,
                         hipStream_t stream);
 // P[p] = bijection(n, keys)(p).
 hipError_t launch_start_perm(int32_t* P, int64_t n, const uint64_t keys[4], hipStream_t stream);
@@ -35,27 +40,27 @@ hipError_t launch_start_perm(int32_t* P, int64_t n, const uint64_t keys[4], hipS
 // must be zeroed beforehand.
 hipError_t launch_check_perm(const int32_t* init, int64_t n, int32_t* counts, int32_t* flag,
                              hipStream_t stream);
-// G[p] = X[P[p]] over dp channels.
-hipError_t launch_gather(const float* X, const int32_t* P, float* G, int64_t n, int dp,
+// G[p] = X[P[p]] over dp channels (P NULL: identity).
+hipError_t launch_gather(const void* X, const int32_t* P, void* G, int64_t n, int dp, int storage,
                          hipStream_t stream);
 // One blur pass (vertical = 0: rows, 1: columns) with the radius of st->r,
 // or `radius` if st is NULL. inv: float32 1/c for c = 0..w.
-hipError_t launch_blur_pass(const float* in, float* out, int w, int dp, const DevState* st,
+hipError_t launch_blur_pass(const void* in, void* out, int w, int dp, int storage, const DevState* st,
                             int radius, int vertical, const float* inv, hipStream_t stream);
 // Grouping table of the current reorder: table[t] = packed pi(t), t < beta^2.
 hipError_t launch_group_table(int32_t* table, const DevState* st, int64_t max_cells,
                               hipStream_t stream);
 // One blockwise assignment with the parameters in st. max_items bounds
 // groups + singles over every level this launch may see.
-hipError_t launch_assign(float* G, const float* T, int32_t* P, const int32_t* table,
-                         DevState* st, int dp, int64_t max_items, hipStream_t stream);
+hipError_t launch_assign(void* G, const void* T, int32_t* P, const int32_t* table, DevState* st, int dp,
+                         int storage, int64_t max_items, hipStream_t stream);
 // Between reorders: the control step of the reorder that ran on `in` (its
 // energy, the stall test, the schedule) written to `out`, and the grouping
 // table of the next reorder. in and out are two different state buffers.
 hipError_t launch_step(const DevState* in, DevState* out, const LevelInfo* levels, plas_level_out* trace,
                        int32_t* table, int64_t max_cells, hipStream_t stream);
 // energy_out (device u64) += sum over cells of floor(d(G[p], T[p]) * 2^s).
-hipError_t launch_energy(const float* G, const float* T, int64_t n, int dp, int s,
+hipError_t launch_energy(const void* G, const void* T, int64_t n, int dp, int storage, int s,
                          unsigned long long* energy_out, hipStream_t stream);
 
 }  // namespace plas

@@ -189,6 +189,8 @@ def test_errors_are_reported(env):
     assert e.value.status == plas.ERR_INVALID_ARGUMENT
     with pytest.raises(plas.PlasError) as e:
         ctx.sort(F, 8, radius_decay=1.5)
+    with pytest.raises(KeyError):
+        ctx.sort(F, 8, storage="fp8")
     assert e.value.status == plas.ERR_INVALID_ARGUMENT
     # The handle still works after errors.
     perm, res = ctx.sort(F, 8, 3)
