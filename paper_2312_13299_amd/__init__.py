@@ -36,13 +36,17 @@ STORAGE_BF16 = 1
 STORAGES = {"f32": STORAGE_F32, "bf16": STORAGE_BF16}
 MAX_CHANNELS = 64
 
-# Every symbol declared in include/plas.h and include/plas_stages.h.
+# Every symbol declared in include/plas.h, include/plas_stages.h and
+# include/plas_batch.h.
 EXPORTS = (
     "plas_get_abi_version", "plas_sort_params_init", "plas_create", "plas_destroy",
     "plas_set_stream", "plas_sort", "plas_grid_energy", "plas_status_string", "plas_last_error",
     "plas_stage_blur", "plas_stage_group_table", "plas_stage_assign", "plas_stage_energy",
     "plas_stage_bijection", "plas_philox4x64_10", "plas_draw", "plas_schedule",
     "plas_scale_shift_from_ranges",
+    "plas_batch_config_init", "plas_sort_batch", "plas_autotune_batch",
+    "plas_job_footprint", "plas_server_create", "plas_server_submit", "plas_server_step",
+    "plas_server_poll", "plas_server_destroy",
 )
 
 
@@ -99,6 +103,61 @@ class SortStats(ctypes.Structure):
     ]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [
+        ("features", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("d", ctypes.c_int32),
+        ("side", ctypes.c_int32),
+        ("layout", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("storage", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("init_perm", ctypes.c_void_p),
+        ("perm_out", ctypes.c_void_p),
+        ("stats", ctypes.POINTER(SortStats)),
+    ]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [
+        ("side_lo", ctypes.c_int32),
+        ("side_hi", ctypes.c_int32),
+        ("blur_waves_per_block", ctypes.c_int32),
+        ("assign_blocks", ctypes.c_int32),
+    ]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("graph", ctypes.c_int32),
+        ("reorders_per_sync", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
+        ("tune_count", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("tune", ctypes.POINTER(TuneEntry)),
+    ]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("sorts", ctypes.c_int32),
+        ("chunks", ctypes.c_int64),
+        ("reorder_slots", ctypes.c_int64),
+        ("graph_builds", ctypes.c_int64),
+        ("launches", ctypes.c_int64),
+        ("prepare_ms", ctypes.c_double),
+        ("loop_ms", ctypes.c_double),
+        ("total_ms", ctypes.c_double),
+        ("step_ms", ctypes.c_double),
+        ("blur_ms", ctypes.c_double),
+        ("assign_ms", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -135,6 +194,18 @@ def library() -> ctypes.CDLL:
         "plas_draw": (None, [u64, u64, u64, u64p]),
         "plas_schedule": (i32, [i32, ctypes.c_double, i32, ctypes.c_double, vp, vp, vp, i32]),
         "plas_scale_shift_from_ranges": (i32, [vp, vp, i32, i64, i32p]),
+        "plas_batch_config_init": (i32, [ctypes.POINTER(BatchConfig)]),
+        "plas_sort_batch": (i32, [vp, ctypes.POINTER(BatchItem), i32, ctypes.POINTER(SortParams),
+                                  ctypes.POINTER(BatchConfig), ctypes.POINTER(BatchStats)]),
+        "plas_autotune_batch": (i32, [vp, ctypes.POINTER(BatchItem), i32, ctypes.POINTER(SortParams), i32,
+                                      ctypes.POINTER(TuneEntry), i32, i32p]),
+        "plas_job_footprint": (i64, [i32, i32, i32, ctypes.POINTER(SortParams)]),
+        "plas_server_create": (i32, [vp, ctypes.POINTER(SortParams), ctypes.POINTER(BatchConfig), i64,
+                                     ctypes.POINTER(vp)]),
+        "plas_server_submit": (i32, [vp, ctypes.POINTER(BatchItem), ctypes.POINTER(ctypes.c_int64)]),
+        "plas_server_step": (i32, [vp, i32p, i32p]),
+        "plas_server_poll": (i32, [vp, ctypes.POINTER(ctypes.c_int64), i32p, i32, i32p]),
+        "plas_server_destroy": (i32, [vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)
@@ -262,41 +333,108 @@ class Context:
         if out is None:
             out = torch.empty(n, dtype=torch.int32, device=features.device)
         _check_tensor(out, torch.int32)
-        prm = SortParams()
-        library().plas_sort_params_init(ctypes.byref(prm))
-        prm.seed = seed & 0xFFFFFFFFFFFFFFFF
-        prm.radius_decay = radius_decay
-        prm.inv_threshold = inv_threshold
-        prm.min_block = min_block
-        prm.start_radius = start_radius
-        prm.max_reorders = max_reorders
-        prm.profile = 1 if profile else 0
-        prm.reorders_per_sync = reorders_per_sync
-        prm.storage = STORAGES[storage]
+        prm = _sort_params(seed=seed, radius_decay=radius_decay, inv_threshold=inv_threshold,
+                           min_block=min_block, start_radius=start_radius, max_reorders=max_reorders,
+                           profile=profile, reorders_per_sync=reorders_per_sync, storage=storage)
         if init_perm is not None:
             _check_tensor(init_perm, torch.int32)
             prm.init_perm = init_perm.data_ptr()
-        cap = 4096
-        trace = (LevelStat * cap)()
-        stats = SortStats()
-        stats.struct_size = ctypes.sizeof(SortStats)
-        stats.trace = ctypes.cast(trace, ctypes.POINTER(LevelStat))
-        stats.trace_cap = cap
+        stats, trace = _new_stats()
         self._bind_stream()
         st = library().plas_sort(self._h, ctypes.c_void_p(features.data_ptr()), n, d, side, lay,
                                  dtype, ctypes.byref(prm), ctypes.c_void_p(out.data_ptr()),
                                  ctypes.byref(stats))
         self._check(st, "plas_sort")
-        res = SortResult(
-            reorders=stats.reorders, levels=stats.levels, energy_fixed=int(stats.energy_fixed),
-            scale_shift=stats.scale_shift, energy=stats.energy,
-            trace=[dict(phi=t.phi, r=t.r, beta=t.beta, reorders=t.reorders,
-                        energy=int(t.energy_fixed), moved=int(t.moved))
-                   for t in trace[: stats.trace_len]],
-            blur_ms=stats.blur_ms, blur_launches=stats.blur_launches,
-            assign_ms=stats.assign_ms, assign_launches=stats.assign_launches,
-            total_ms=stats.total_ms)
-        return out, res
+        return out, _result(stats, trace)
+
+    # ---- batches
+
+    def _batch_items(self, features_list, sides, seeds, layouts, storages, init_perms, outs):
+        import torch
+        count = len(features_list)
+        def per(v, name):
+            if isinstance(v, (list, tuple)):
+                if len(v) != count:
+                    raise ValueError(f"{name}: {len(v)} values for {count} sorts")
+                return list(v)
+            return [v] * count
+        sides, seeds, layouts = per(sides, "sides"), per(seeds, "seeds"), per(layouts, "layouts")
+        storages, init_perms = per(storages, "storages"), per(init_perms, "init_perms")
+        outs = per(outs, "out")
+        items = (BatchItem * max(count, 1))()
+        keep = []
+        for i, f in enumerate(features_list):
+            dtype = _feature_dtype(f)
+            if layouts[i] == "cn":
+                d, n = f.shape
+                lay = LAYOUT_CN
+            elif layouts[i] == "nc":
+                n, d = f.shape
+                lay = LAYOUT_NC
+            else:
+                raise ValueError(f"unknown layout {layouts[i]!r}")
+            side = sides[i] if sides[i] is not None else int(round(n ** 0.5))
+            out = outs[i]
+            if out is None:
+                out = torch.empty(n, dtype=torch.int32, device=f.device)
+            _check_tensor(out, torch.int32)
+            stats, trace = _new_stats()
+            it = items[i]
+            it.features = f.data_ptr()
+            it.n, it.d, it.side, it.layout, it.dtype = n, d, side, lay, dtype
+            it.storage = STORAGES[storages[i]]
+            it.seed = int(seeds[i]) & 0xFFFFFFFFFFFFFFFF
+            if init_perms[i] is not None:
+                _check_tensor(init_perms[i], torch.int32)
+                it.init_perm = init_perms[i].data_ptr()
+            it.perm_out = out.data_ptr()
+            it.stats = ctypes.pointer(stats)
+            keep.append((out, stats, trace))
+        return items, keep
+
+    def sort_batch(self, features_list, sides=None, seeds=0x5EED, layouts="cn", storages="f32",
+                   init_perms=None, *, graph: bool = False, tune=None, reorders_per_sync: int = 0,
+                   profile: bool = False, radius_decay: float = 0.95, inv_threshold: int = 10000,
+                   min_block: int = 16, start_radius: float = 0.0, max_reorders: int = 0, out=None):
+        """Sort several grids together (plas_sort_batch). Per-sort arguments
+        (sides, seeds, layouts, storages, init_perms, out) take one value for
+        all or a list. tune: list of dicts with side_lo, side_hi,
+        blur_waves_per_block, assign_blocks (as autotune_batch returns).
+        Returns (perms, results, BatchResult)."""
+        count = len(features_list)
+        items, keep = self._batch_items(features_list, sides, seeds, layouts, storages, init_perms, out)
+        prm = _sort_params(radius_decay=radius_decay, inv_threshold=inv_threshold, min_block=min_block,
+                           start_radius=start_radius, max_reorders=max_reorders)
+        cfg, table = _batch_config(graph, reorders_per_sync, profile, tune)
+        bstats = BatchStats()
+        bstats.struct_size = ctypes.sizeof(BatchStats)
+        self._bind_stream()
+        st = library().plas_sort_batch(self._h, items, count, ctypes.byref(prm), ctypes.byref(cfg),
+                                       ctypes.byref(bstats))
+        self._check(st, "plas_sort_batch")
+        perms = [k[0] for k in keep]
+        results = [_result(k[1], k[2]) for k in keep]
+        b = BatchResult(**{name: getattr(bstats, name) for name, _ in BatchStats._fields_
+                           if name != "struct_size"})
+        return perms, results, b
+
+    def autotune_batch(self, features_list, sides=None, seeds=0x5EED, layouts="cn", storages="f32", *,
+                       graph: bool = False, radius_decay: float = 0.95, inv_threshold: int = 10000,
+                       min_block: int = 16):
+        """Measured launch shapes per side bucket for these grids
+        (plas_autotune_batch): a list of dicts for sort_batch(tune=...)."""
+        count = len(features_list)
+        items, keep = self._batch_items(features_list, sides, seeds, layouts, storages, None, None)
+        prm = _sort_params(radius_decay=radius_decay, inv_threshold=inv_threshold, min_block=min_block)
+        cap = 64
+        table = (TuneEntry * cap)()
+        entries = ctypes.c_int32()
+        self._bind_stream()
+        st = library().plas_autotune_batch(self._h, items, count, ctypes.byref(prm), 1 if graph else 0, table,
+                                           cap, ctypes.byref(entries))
+        self._check(st, "plas_autotune_batch")
+        return [dict(side_lo=t.side_lo, side_hi=t.side_hi, blur_waves_per_block=t.blur_waves_per_block,
+                     assign_blocks=t.assign_blocks) for t in table[: entries.value]]
 
     def grid_energy(self, features, perm=None, side: int | None = None, radius: int = 1,
                     layout: str = "cn", storage: str = "f32"):
@@ -398,6 +536,157 @@ class SortResult:
     assign_ms: float = 0.0
     assign_launches: int = 0
     total_ms: float = 0.0
+
+
+def _batch_config(graph: bool, reorders_per_sync: int, profile: bool, tune):
+    cfg = BatchConfig()
+    library().plas_batch_config_init(ctypes.byref(cfg))
+    cfg.graph = 1 if graph else 0
+    cfg.reorders_per_sync = reorders_per_sync
+    cfg.profile = 1 if profile else 0
+    table = None
+    if tune:
+        table = (TuneEntry * len(tune))()
+        for i, e in enumerate(tune):
+            table[i].side_lo, table[i].side_hi = e["side_lo"], e["side_hi"]
+            table[i].blur_waves_per_block = e.get("blur_waves_per_block", 0)
+            table[i].assign_blocks = e.get("assign_blocks", 0)
+        cfg.tune = ctypes.cast(table, ctypes.POINTER(TuneEntry))
+        cfg.tune_count = len(tune)
+    return cfg, table
+
+
+def job_footprint(side: int, d: int, storage: str = "f32", **params) -> int:
+    """Device bytes one served job holds while it runs."""
+    prm = _sort_params(**params)
+    v = library().plas_job_footprint(side, d, STORAGES[storage], ctypes.byref(prm))
+    if v < 0:
+        raise PlasError(int(v), "bad job arguments")
+    return int(v)
+
+
+class Server:
+    """Continuous-batching sort server on a Context (plas_server_*): submit
+    jobs at any time; each step() admits waiting jobs whose device memory
+    fits in the budget, runs one chunk of reorders of every running job and
+    collects finished ones; poll() returns them."""
+
+    def __init__(self, ctx: "Context", memory_budget: int, *, graph: bool = False, reorders_per_sync: int = 0,
+                 tune=None, radius_decay: float = 0.95, inv_threshold: int = 10000, min_block: int = 16,
+                 start_radius: float = 0.0, max_reorders: int = 0):
+        self.ctx = ctx
+        self._h = ctypes.c_void_p()
+        prm = _sort_params(radius_decay=radius_decay, inv_threshold=inv_threshold, min_block=min_block,
+                           start_radius=start_radius, max_reorders=max_reorders)
+        cfg, self._table = _batch_config(graph, reorders_per_sync, False, tune)
+        ctx._bind_stream()
+        st = library().plas_server_create(ctx._h, ctypes.byref(prm), ctypes.byref(cfg), int(memory_budget),
+                                          ctypes.byref(self._h))
+        ctx._check(st, "plas_server_create")
+        self._jobs = {}
+
+    def submit(self, features, side: int | None = None, seed: int = 0x5EED, layout: str = "cn",
+               storage: str = "f32", init_perm=None, out=None) -> int:
+        items, keep = self.ctx._batch_items([features], [side], [seed], [layout], [storage], [init_perm], [out])
+        job = ctypes.c_int64()
+        st = library().plas_server_submit(self._h, ctypes.byref(items[0]), ctypes.byref(job))
+        self.ctx._check(st, "plas_server_submit")
+        # The buffers stay referenced until the job is polled.
+        self._jobs[job.value] = (features, init_perm, items, keep[0])
+        return job.value
+
+    def step(self) -> tuple[int, int]:
+        running, waiting = ctypes.c_int32(), ctypes.c_int32()
+        self.ctx._bind_stream()
+        st = library().plas_server_step(self._h, ctypes.byref(running), ctypes.byref(waiting))
+        self.ctx._check(st, "plas_server_step")
+        return running.value, waiting.value
+
+    def poll(self):
+        """[(job_id, status, perm, SortResult or None)] of the jobs finished
+        or failed since the last poll."""
+        cap = 256
+        ids = (ctypes.c_int64 * cap)()
+        sts = (ctypes.c_int32 * cap)()
+        out = []
+        while True:
+            n = ctypes.c_int32()
+            st = library().plas_server_poll(self._h, ids, sts, cap, ctypes.byref(n))
+            self.ctx._check(st, "plas_server_poll")
+            for i in range(n.value):
+                _, _, _, (perm, stats, trace) = self._jobs.pop(ids[i])
+                ok = sts[i] == OK
+                out.append((ids[i], sts[i], perm if ok else None, _result(stats, trace) if ok else None))
+            if n.value < cap:
+                return out
+
+    def close(self):
+        if self._h:
+            library().plas_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._jobs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class BatchResult:
+    sorts: int
+    chunks: int
+    reorder_slots: int
+    graph_builds: int
+    launches: int
+    prepare_ms: float
+    loop_ms: float
+    total_ms: float
+    step_ms: float
+    blur_ms: float
+    assign_ms: float
+
+
+def _sort_params(seed: int = 0x5EED, radius_decay: float = 0.95, inv_threshold: int = 10000,
+                 min_block: int = 16, start_radius: float = 0.0, max_reorders: int = 0,
+                 profile: bool = False, reorders_per_sync: int = 0, storage: str = "f32") -> SortParams:
+    prm = SortParams()
+    library().plas_sort_params_init(ctypes.byref(prm))
+    prm.seed = seed & 0xFFFFFFFFFFFFFFFF
+    prm.radius_decay = radius_decay
+    prm.inv_threshold = inv_threshold
+    prm.min_block = min_block
+    prm.start_radius = start_radius
+    prm.max_reorders = max_reorders
+    prm.profile = 1 if profile else 0
+    prm.reorders_per_sync = reorders_per_sync
+    prm.storage = STORAGES[storage]
+    return prm
+
+
+TRACE_CAP = 4096
+
+
+def _new_stats():
+    trace = (LevelStat * TRACE_CAP)()
+    stats = SortStats()
+    stats.struct_size = ctypes.sizeof(SortStats)
+    stats.trace = ctypes.cast(trace, ctypes.POINTER(LevelStat))
+    stats.trace_cap = TRACE_CAP
+    return stats, trace
+
+
+def _result(stats: SortStats, trace) -> SortResult:
+    return SortResult(
+        reorders=stats.reorders, levels=stats.levels, energy_fixed=int(stats.energy_fixed),
+        scale_shift=stats.scale_shift, energy=stats.energy,
+        trace=[dict(phi=t.phi, r=t.r, beta=t.beta, reorders=t.reorders,
+                    energy=int(t.energy_fixed), moved=int(t.moved))
+               for t in trace[: stats.trace_len]],
+        blur_ms=stats.blur_ms, blur_launches=stats.blur_launches,
+        assign_ms=stats.assign_ms, assign_launches=stats.assign_launches,
+        total_ms=stats.total_ms)
 
 
 def _feature_dtype(t) -> int:

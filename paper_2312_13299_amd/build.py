@@ -19,7 +19,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 LIBRARY = os.path.join(HERE, "libplas.so")
 ARCH = os.environ.get("PLAS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["plas_kernels.hip", "plas_engine.cpp"]
+SOURCES = ["plas_kernels.hip", "plas_engine.cpp", "plas_batch.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC",

@@ -69,4 +69,25 @@ struct HostStatus {
   int64_t k;
 };
 
+struct plas_level_out;
+
+// One sort of a batch: its buffers, its two states (each reorder's step
+// reads one and writes the other), and how many blocks of each launch kind
+// it takes. Grids G, H, T are [w*w][dp] in the batch's storage.
+struct BatchGrid {
+  void* G;
+  void* H;
+  void* T;
+  int32_t* P;
+  int32_t* table;
+  const float* inv;
+  const LevelInfo* levels;
+  plas_level_out* trace;
+  DevState* states;
+  int32_t w;
+  int32_t step_blocks;
+  int32_t blur_blocks;
+  int32_t assign_blocks;
+};
+
 }  // namespace plas

@@ -20,257 +20,13 @@
 #include <string>
 #include <vector>
 
-#include "plas.h"
-#include "plas_device.h"
-#include "plas_launch.h"
-#include "plas_random.h"
+#include "plas_host.h"
 #include "plas_stages.h"
 
-using plas::DevState;
-using plas::HostStatus;
-using plas::LevelInfo;
-using plas::plas_level_out;
+using namespace plas_host;
 
 static_assert(sizeof(plas_level_out) == sizeof(plas_level_stat), "trace entry layout");
 
-namespace {
-
-constexpr int kDefaultReordersPerSync = 32;
-
-struct DeviceBuffer {
-  void* ptr = nullptr;
-  size_t bytes = 0;
-};
-
-}  // namespace
-
-struct plas_context {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  std::string error;
-  // Device workspace, grown on demand and kept.
-  DeviceBuffer grid_g, grid_h, grid_t;  // [n][dp] each, float32 or bfloat16
-  DeviceBuffer perm;                    // int32[n]
-  DeviceBuffer table;                   // int32[beta^2]
-  DeviceBuffer inv;                     // float32 1/c, c = 0..w
-  DeviceBuffer range_part, range_out;   // range pass scratch and result
-  DeviceBuffer levels;                  // LevelInfo[levels]
-  DeviceBuffer trace;                   // plas_level_out[levels]
-  DeviceBuffer state;                   // two DevStates of a sort (read one, write the other)
-  DeviceBuffer stage_state;             // DevState of a stage call
-  DeviceBuffer scratch;                 // u64 accumulators and flags
-  // Pinned host memory for small read-backs.
-  HostStatus* status_host = nullptr;
-  float* range_host = nullptr;
-  unsigned long long* u64_host = nullptr;
-  DevState* state_host = nullptr;
-  std::vector<hipEvent_t> events;
-};
-
-namespace {
-
-// ---------------------------------------------------------------- helpers
-
-int32_t fail(plas_context* h, int32_t status, const std::string& msg) {
-  if (h != nullptr) h->error = msg;
-  return status;
-}
-
-int32_t hip_fail(plas_context* h, hipError_t e, const char* what) {
-  std::string msg = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
-  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
-    return fail(h, PLAS_ERR_OUT_OF_MEMORY, msg);
-  return fail(h, PLAS_ERR_HIP, msg);
-}
-
-#define PLAS_HIP(h, call)                                  \
-  do {                                                     \
-    hipError_t e_ = (call);                                \
-    if (e_ != hipSuccess) return hip_fail((h), e_, #call); \
-  } while (0)
-
-// Keeps the caller's current device and restores it on exit.
-class DeviceScope {
- public:
-  explicit DeviceScope(int device) {
-    if (hipGetDevice(&saved_) != hipSuccess) saved_ = -1;
-    ok_ = hipSetDevice(device) == hipSuccess;
-  }
-  ~DeviceScope() {
-    if (saved_ >= 0) (void)hipSetDevice(saved_);
-  }
-  bool ok() const { return ok_; }
-
- private:
-  int saved_ = -1;
-  bool ok_ = false;
-};
-
-hipError_t reserve(DeviceBuffer& b, size_t bytes) {
-  if (bytes <= b.bytes && b.ptr != nullptr) return hipSuccess;
-  if (b.ptr != nullptr) {
-    hipError_t e = hipFree(b.ptr);
-    b.ptr = nullptr;
-    b.bytes = 0;
-    if (e != hipSuccess) return e;
-  }
-  hipError_t e = hipMalloc(&b.ptr, bytes);
-  if (e != hipSuccess) {
-    b.ptr = nullptr;
-    return e;
-  }
-  b.bytes = bytes;
-  return hipSuccess;
-}
-
-void release(DeviceBuffer& b) {
-  if (b.ptr != nullptr) (void)hipFree(b.ptr);
-  b.ptr = nullptr;
-  b.bytes = 0;
-}
-
-template <typename T>
-T* as(DeviceBuffer& b) {
-  return static_cast<T*>(b.ptr);
-}
-
-size_t storage_bytes(int32_t storage) { return storage == PLAS_STORAGE_BF16 ? 2 : 4; }
-
-bool valid_storage(int32_t storage) { return storage == PLAS_STORAGE_F32 || storage == PLAS_STORAGE_BF16; }
-
-int padded_channels(int d) {
-  int dp = 4;
-  while (dp < d) dp *= 2;
-  return dp;
-}
-
-// The radius schedule of Sec. 3.1 with the block geometry of each level.
-int32_t build_schedule(int32_t w, double decay, int32_t min_block, double start_radius,
-                       std::vector<LevelInfo>* out) {
-  if (w < 1 || !(decay > 0.0 && decay < 1.0) || min_block < 1) return PLAS_ERR_INVALID_ARGUMENT;
-  double phi = start_radius > 0.0 ? start_radius : static_cast<double>(w) / 2.0 - 1.0;
-  if (!(phi >= 1.0)) phi = 1.0;  // also catches NaN
-  out->clear();
-  while (phi >= 1.0) {
-    LevelInfo lv{};
-    lv.phi = phi;
-    // r beyond w - 1 blurs whole lines; the cap only keeps x + r in range.
-    const double rf = std::floor(phi);
-    lv.r = rf > 1073741824.0 ? 1073741824 : static_cast<int32_t>(rf);
-    lv.beta = std::min(w, std::max(min_block, lv.r + 1));
-    lv.nb = w / lv.beta;
-    const int64_t cells = static_cast<int64_t>(lv.beta) * lv.beta;
-    lv.groups_per_block = cells / 4;
-    lv.groups = static_cast<int64_t>(lv.nb) * lv.nb * lv.groups_per_block;
-    const int64_t covered = static_cast<int64_t>(lv.nb) * lv.beta;
-    lv.singles = static_cast<int64_t>(w) * w - covered * covered +
-                 static_cast<int64_t>(lv.nb) * lv.nb * (cells % 4);
-    out->push_back(lv);
-    phi = phi * decay;
-  }
-  return PLAS_OK;
-}
-
-int32_t scale_shift(const float* mins, const float* maxs, int32_t d, int64_t n) {
-  double dmax = 0.0;
-  for (int32_t c = 0; c < d; ++c) {
-    const double span = static_cast<double>(maxs[c]) - static_cast<double>(mins[c]);
-    dmax += span * span;
-  }
-  if (!(dmax > 0.0)) return 0;
-  int e = 0;
-  (void)std::frexp(static_cast<double>(n) * dmax, &e);
-  return 61 - e;
-}
-
-bool valid_layout(int32_t layout) { return layout == PLAS_LAYOUT_CN || layout == PLAS_LAYOUT_NC; }
-
-// Shared argument checks of plas_sort and plas_grid_energy.
-int32_t check_features(plas_context* h, const void* features, int64_t n, int32_t d, int32_t side,
-                       int32_t layout, int32_t dtype) {
-  if (h == nullptr) return PLAS_ERR_INVALID_ARGUMENT;
-  if (features == nullptr) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "features is NULL");
-  if (side < 2 || side > 46340) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "side must be in [2, 46340]");
-  if (n != static_cast<int64_t>(side) * side)
-    return fail(h, PLAS_ERR_INVALID_ARGUMENT, "n must equal side * side");
-  if (d < 1) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "d must be >= 1");
-  if (!valid_layout(layout)) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "unknown layout");
-  if (dtype != PLAS_DTYPE_F32 && dtype != PLAS_DTYPE_BF16) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "unknown dtype");
-  if (d > PLAS_MAX_CHANNELS)
-    return fail(h, PLAS_ERR_UNSUPPORTED, "d above PLAS_MAX_CHANNELS is not supported");
-  return PLAS_OK;
-}
-
-// Ingest + range + scale shift, leaving X (cell-major padded features) in
-// grid_t. Returns NONFINITE if a value is not finite.
-int32_t prepare_features(plas_context* h, const void* features, int32_t dtype, int64_t n, int32_t d,
-                         int32_t layout, int dp, int32_t storage, int32_t* s_out) {
-  const size_t grid_bytes = static_cast<size_t>(n) * dp * storage_bytes(storage);
-  PLAS_HIP(h, reserve(h->grid_g, grid_bytes));
-  PLAS_HIP(h, reserve(h->grid_h, grid_bytes));
-  PLAS_HIP(h, reserve(h->grid_t, grid_bytes));
-  PLAS_HIP(h, reserve(h->range_part, plas::range_partial_floats(dp) * sizeof(float)));
-  PLAS_HIP(h, reserve(h->range_out, (2 * 64 + 1) * sizeof(float)));
-  void* X = h->grid_t.ptr;
-  PLAS_HIP(h, plas::launch_ingest(features, dtype == PLAS_DTYPE_BF16, n, d, layout, dp, storage, X, h->stream));
-  PLAS_HIP(h, plas::launch_range(X, n, d, dp, storage, as<float>(h->range_part), as<float>(h->range_out),
-                                 h->stream));
-  PLAS_HIP(h, hipMemcpyAsync(h->range_host, h->range_out.ptr, (2 * dp + 1) * sizeof(float),
-                             hipMemcpyDeviceToHost, h->stream));
-  PLAS_HIP(h, hipStreamSynchronize(h->stream));
-  if (h->range_host[2 * dp] != 0.0f)
-    return fail(h, PLAS_ERR_NONFINITE, "features contain NaN or infinity");
-  *s_out = scale_shift(h->range_host, h->range_host + dp, d, n);
-  return PLAS_OK;
-}
-
-// Validate a caller permutation (device int32[n]); uses grid_h as scratch
-// (at least n * 4 * 2 bytes in either storage).
-int32_t check_permutation(plas_context* h, const int32_t* perm, int64_t n) {
-  int32_t* counts = as<int32_t>(h->grid_h);
-  int32_t* flag = reinterpret_cast<int32_t*>(as<unsigned long long>(h->scratch) + 8);
-  PLAS_HIP(h, hipMemsetAsync(counts, 0, static_cast<size_t>(n) * sizeof(int32_t), h->stream));
-  PLAS_HIP(h, hipMemsetAsync(flag, 0, sizeof(int32_t), h->stream));
-  PLAS_HIP(h, plas::launch_check_perm(perm, n, counts, flag, h->stream));
-  PLAS_HIP(h, hipMemcpyAsync(h->u64_host, flag, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-  PLAS_HIP(h, hipStreamSynchronize(h->stream));
-  int32_t bad = 0;
-  std::memcpy(&bad, h->u64_host, sizeof(int32_t));
-  if (bad != 0) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "permutation is not a bijection of [0, n)");
-  return PLAS_OK;
-}
-
-int32_t upload_inverse_counts(plas_context* h, int32_t w) {
-  PLAS_HIP(h, reserve(h->inv, static_cast<size_t>(w + 1) * sizeof(float)));
-  std::vector<float> inv(static_cast<size_t>(w) + 1);
-  inv[0] = 0.0f;
-  for (int32_t c = 1; c <= w; ++c) inv[c] = 1.0f / static_cast<float>(c);
-  PLAS_HIP(h, hipMemcpyAsync(h->inv.ptr, inv.data(), inv.size() * sizeof(float), hipMemcpyHostToDevice,
-                             h->stream));
-  // The source vector dies at return; make the copy complete first.
-  PLAS_HIP(h, hipStreamSynchronize(h->stream));
-  return PLAS_OK;
-}
-
-int32_t ensure_events(plas_context* h, size_t count) {
-  while (h->events.size() < count) {
-    hipEvent_t e;
-    PLAS_HIP(h, hipEventCreate(&e));
-    h->events.push_back(e);
-  }
-  return PLAS_OK;
-}
-
-void fill_state_for_level(DevState* s, const LevelInfo& lv) {
-  s->r = lv.r;
-  s->beta = lv.beta;
-  s->nb = lv.nb;
-  s->groups_per_block = lv.groups_per_block;
-  s->groups = lv.groups;
-  s->singles = lv.singles;
-}
-
-}  // namespace
 
 // ======================================================================== C ABI
 
@@ -344,6 +100,7 @@ int32_t plas_destroy(plas_handle h) {
   if (h->stream != nullptr) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+  release_batch_state(h);
   DeviceBuffer* bufs[] = {&h->grid_g, &h->grid_h, &h->grid_t, &h->perm, &h->table, &h->inv,
                           &h->range_part, &h->range_out, &h->levels, &h->trace, &h->state,
                           &h->stage_state, &h->scratch};
@@ -371,18 +128,8 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
   h->error.clear();
   if (perm_out == nullptr) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "perm_out is NULL");
   plas_sort_params prm;
-  plas_sort_params_init(&prm);
-  if (params != nullptr) {
-    if (params->struct_size != sizeof(plas_sort_params))
-      return fail(h, PLAS_ERR_INVALID_ARGUMENT, "params->struct_size does not match this library");
-    prm = *params;
-  }
-  if (!(prm.radius_decay > 0.0 && prm.radius_decay < 1.0))
-    return fail(h, PLAS_ERR_INVALID_ARGUMENT, "radius_decay must be in (0, 1)");
-  if (prm.inv_threshold < 1) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "inv_threshold must be >= 1");
-  if (prm.min_block < 1) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "min_block must be >= 1");
-  if (prm.max_reorders < 0) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "max_reorders must be >= 0");
-  if (!valid_storage(prm.storage)) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "unknown storage");
+  st = check_params(h, params, &prm);
+  if (st != PLAS_OK) return st;
   if (stats != nullptr && stats->struct_size != sizeof(plas_sort_stats))
     return fail(h, PLAS_ERR_INVALID_ARGUMENT, "stats->struct_size does not match this library");
 
@@ -423,7 +170,7 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
   // Start arrangement: the caller's, or the keyed bijection of draw
   // (seed, 0, 0) (random positions, Sec. 3.1).
   if (prm.init_perm != nullptr) {
-    st = check_permutation(h, prm.init_perm, n);
+    st = check_permutation(h, prm.init_perm, n, as<int32_t>(h->grid_h));
     if (st != PLAS_OK) return st;
     PLAS_HIP(h, hipMemcpyAsync(P, prm.init_perm, static_cast<size_t>(n) * sizeof(int32_t),
                                hipMemcpyDeviceToDevice, h->stream));
@@ -435,18 +182,7 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
 
   // First reorder's state.
   DevState* S = h->state_host;
-  std::memset(S, 0, sizeof(DevState));
-  S->w = w;
-  S->s = s;
-  fill_state_for_level(S, levels[0]);
-  S->nlevels = static_cast<int32_t>(levels.size());
-  S->inv_threshold = prm.inv_threshold;
-  S->max_reorders = prm.max_reorders;
-  S->seed = prm.seed;
-  plas::block_shift(prm.seed, 0, w, &S->dy, &S->dx);
-  S->j = 1;
-  const plas::Words4 keys = plas::draw(prm.seed, plas::kDrawGrouping, 0);
-  for (int i = 0; i < 4; ++i) S->keys[i] = keys.v[i];
+  init_sort_state(S, w, s, levels, prm, prm.seed);
   // State buffers: each reorder's step launch reads states[cur] and writes
   // states[cur ^ 1], which the reorder's kernels then use.
   DevState* states = as<DevState>(h->state);
@@ -462,9 +198,7 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
     st = ensure_events(h, static_cast<size_t>(chunk) * 4);
     if (st != PLAS_OK) return st;
   }
-  // Improvements per level are at most about M * ln(2^62); two stalls end it.
-  const int64_t reorder_bound =
-      static_cast<int64_t>(levels.size()) * (static_cast<int64_t>(prm.inv_threshold) * 44 + 3);
+  const int64_t max_k = reorder_bound(levels.size(), prm.inv_threshold);
   double blur_ms = 0.0, assign_ms = 0.0;
   int64_t timed_reorders = 0;
   int64_t slots = 0;  // reorder slots queued so far; slot i runs reorder i unless the sort has ended
@@ -509,7 +243,7 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
     // short the device state is broken. Also stop at the bound on reorders
     // that the stall test implies (energies strictly fall by at least 1/M per
     // improvement, two stalls end a level).
-    if (k_now < slots - 1 || k_now > reorder_bound)
+    if (k_now < slots - 1 || k_now > max_k)
       return fail(h, PLAS_ERR_HIP, "device controller made no progress");
   }
 
@@ -558,7 +292,7 @@ int32_t plas_grid_energy(plas_handle h, const void* features, const int32_t* per
   st = prepare_features(h, features, dtype, n, d, layout, dp, storage, &s);
   if (st != PLAS_OK) return st;
   if (perm != nullptr) {
-    st = check_permutation(h, perm, n);
+    st = check_permutation(h, perm, n, as<int32_t>(h->grid_h));
     if (st != PLAS_OK) return st;
   }
   st = upload_inverse_counts(h, side);

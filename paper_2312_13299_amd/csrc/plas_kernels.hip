@@ -17,6 +17,8 @@
 // equal, bit for bit, to a CPU that evaluates the same expressions.
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+
 #include "plas_launch.h"
 #include "plas_random.h"
 
@@ -28,9 +30,6 @@ constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kRangeBlocks = 256;
 #ifndef PLAS_ASSIGN_MAX_BLOCKS
 #define PLAS_ASSIGN_MAX_BLOCKS 4096
-#endif
-#ifndef PLAS_STAGE_DEPTH
-#define PLAS_STAGE_DEPTH 4
 #endif
 #ifndef PLAS_BLUR_LINES_PER_WAVE
 #define PLAS_BLUR_LINES_PER_WAVE 1
@@ -320,15 +319,12 @@ __device__ __forceinline__ void blur_range(const L_t& L, int xb, int xe, float& 
   }
 }
 
+// Lines wave * 64/DP .. of one pass, by wave `wave` of the pass.
 template <int DP, typename S>
-__global__ __launch_bounds__(kBlock) void k_blur(const S* __restrict__ in, S* __restrict__ out,
-                                                 int w, const DevState* __restrict__ st, int radius,
-                                                 int vertical, const float* __restrict__ inv) {
-  if (st != nullptr && st->done) return;
-  const int r = st != nullptr ? st->r : radius;
+__device__ __forceinline__ void blur_reg_lines(const S* __restrict__ in, S* __restrict__ out, int w, int r,
+                                               int vertical, const float* __restrict__ inv, int64_t wave,
+                                               int lane) {
   constexpr int LPW = 64 / DP;
-  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
   const int64_t line = wave * LPW + lane / DP;
   const int c = lane % DP;
   if (line >= w) return;
@@ -372,197 +368,204 @@ __global__ __launch_bounds__(kBlock) void k_blur(const S* __restrict__ in, S* __
   }
 }
 
+// Waves of one pass for DP < 64 (64 / DP lines per wave).
+template <int DP>
+inline int64_t blur_reg_waves(int w) {
+  return (w + 64 / DP - 1) / (64 / DP);
+}
+
+template <int DP, typename S>
+__global__ __launch_bounds__(kBlock) void k_blur(const S* __restrict__ in, S* __restrict__ out,
+                                                 int w, const DevState* __restrict__ st, int radius,
+                                                 int vertical, const float* __restrict__ inv) {
+  if (st != nullptr && st->done) return;
+  const int r = st != nullptr ? st->r : radius;
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 6;
+  blur_reg_lines<DP, S>(in, out, w, r, vertical, inv, wave, threadIdx.x & 63);
+}
+
 // Blur pass for 64-channel cells, staged through LDS. Same arithmetic as
-// k_blur (one running sum per line and channel, same operation order), but
-// the memory side is reorganised: a per-position load of one channel per lane
-// can only keep one position of 64 chains in flight per instruction, which
-// caps the bytes in flight far below what HBM needs. Here every lane loads
-// 16 bytes (4 float32 or 8 bfloat16 channels) of one of kPos consecutive
-// positions, so one instruction brings 4 (float32) or 8 (bfloat16) positions
-// of the wave's line; kStageChunk positions of the entering and of the
-// leaving stream go through LDS as float32, where lane = channel reads them
-// back in order. Outputs return through LDS and leave as 16-byte stores
-// (rounded to the storage type). The loads of the next kStageDepth - 1
-// chunks are in flight while the current one is summed. One wave per line,
-// four lines per block.
-constexpr int kStageChunk = 32;
-constexpr int kStageDepth = PLAS_STAGE_DEPTH;  // chunks whose loads are in flight
+// k_blur (one running sum per line and channel, same operation order), with
+// the memory side reorganised. A per-position load of one channel per lane
+// keeps only one position of the 64 chains in flight per instruction, far
+// below what HBM needs. Here every lane loads 16 bytes (4 float32 or 8
+// bfloat16 channels) of one of kPos consecutive cells, so one instruction
+// fetches kPos whole positions of the wave's line. A chunk of kChunk
+// positions of the entering and of the leaving stream (8 KB each in either
+// storage) is copied raw into LDS, where lane = channel reads it back in
+// order; outputs return through LDS and leave as 16-byte stores.
+//
+// Loads are issued unconditionally, at addresses clamped into the line (a
+// clamped load fetches a value the sums never use), so a chunk's fetch is
+// straight-line code: the next chunk's loads are issued right after the
+// current chunk has been copied to LDS and are in flight while it is summed.
+constexpr int kStageSub = 32;  // positions summed per pass over LDS
 
 template <typename S>
 struct StagedShape {
   static constexpr int kChannels = 16 / static_cast<int>(sizeof(S));  // channels per 16-byte load
   static constexpr int kLanesPerCell = 64 / kChannels;
   static constexpr int kPos = 64 / kLanesPerCell;  // positions per load instruction
-  static constexpr int kVec = kStageChunk / kPos;  // loads per stream per chunk
+  static constexpr int kVec = 8;                   // loads per stream per chunk
+  static constexpr int kChunk = kVec * kPos;       // 32 (float32) or 64 (bfloat16) positions
+  static_assert(kChunk % kStageSub == 0 && kChunk <= 64, "chunk shape");
+};
+
+// LDS of one wave: 24 KB in either storage.
+template <typename S>
+struct StagedLds {
+  S enter[StagedShape<S>::kChunk][64];
+  S leave[StagedShape<S>::kChunk][64];
+  S out[StagedShape<S>::kChunk][64];
 };
 
 template <typename S>
 struct StagedRegs {
   uint4 enter[StagedShape<S>::kVec];
   uint4 leave[StagedShape<S>::kVec];
-  float mult;  // lane p < kStageChunk: float32(1/count) of the chunk's position p
+  float mult;  // lane p < kChunk: float32(1/count) of the chunk's position p
 };
-
-// 16 loaded bytes of one position to float32 channels in LDS, and back.
-__device__ __forceinline__ void stage_in(float* row, const uint4 v, float) {
-  *reinterpret_cast<uint4*>(row) = v;
-}
-__device__ __forceinline__ void stage_in(float* row, const uint4 v, uint16_t) {
-  *reinterpret_cast<float4*>(row) =
-      make_float4(bf16_to_float(v.x & 0xffffu), bf16_to_float(v.x >> 16), bf16_to_float(v.y & 0xffffu),
-                  bf16_to_float(v.y >> 16));
-  *reinterpret_cast<float4*>(row + 4) =
-      make_float4(bf16_to_float(v.z & 0xffffu), bf16_to_float(v.z >> 16), bf16_to_float(v.w & 0xffffu),
-                  bf16_to_float(v.w >> 16));
-}
-__device__ __forceinline__ uint4 stage_out(const float* row, float) {
-  return *reinterpret_cast<const uint4*>(row);
-}
-__device__ __forceinline__ uint4 stage_out(const float* row, uint16_t) {
-  uint4 v;
-  v.x = float_to_bf16(row[0]) | (float_to_bf16(row[1]) << 16);
-  v.y = float_to_bf16(row[2]) | (float_to_bf16(row[3]) << 16);
-  v.z = float_to_bf16(row[4]) | (float_to_bf16(row[5]) << 16);
-  v.w = float_to_bf16(row[6]) | (float_to_bf16(row[7]) << 16);
-  return v;
-}
 
 template <typename S>
 struct StagedLine {
   using Shape = StagedShape<S>;
+  static constexpr int kChunk = Shape::kChunk;
   const S* __restrict__ src;
   S* __restrict__ dst;
   const float* __restrict__ inv;
   int64_t step;
-  int w, r, first_hi, n_init;
+  int w, r, first_hi, n_init, n_chunks;
   int q, j, lane;
-  float (*s_enter)[64];
-  float (*s_leave)[64];
-  float (*s_out)[64];
+  StagedLds<S>* lds;
+
+  __device__ __forceinline__ int clamp_pos(int t) const { return t < 0 ? 0 : (t > w - 1 ? w - 1 : t); }
 
   __device__ __forceinline__ uint4 ld(int t) const {
     return reinterpret_cast<const uint4*>(src + static_cast<int64_t>(t) * step)[j];
   }
 
-  // Chunks 0 .. n_init-1 cover positions 0 .. first_hi of the starting sum;
-  // chunk n_init + k covers output positions 1 + k*kStageChunk onwards.
+  // Chunks 0 .. n_init-1 cover positions 0 .. first_hi of the starting sum
+  // (entering stream only); chunk n_init + k covers output positions
+  // 1 + k*kChunk onwards.
   __device__ __forceinline__ void fetch(int c, StagedRegs<S>& R) const {
-    const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
-    if (c < n_init) {
+    const bool init = c < n_init;
+    const int base = init ? c * kChunk : 1 + (c - n_init) * kChunk;
 #pragma unroll
-      for (int i = 0; i < Shape::kVec; ++i) {
-        const int t = c * kStageChunk + Shape::kPos * i + q;
-        R.enter[i] = t <= first_hi ? ld(t) : zero;
-        R.leave[i] = zero;
-      }
-      R.mult = 0.0f;
-    } else {
-      const int x0 = 1 + (c - n_init) * kStageChunk;
+    for (int i = 0; i < Shape::kVec; ++i) {
+      const int x = base + Shape::kPos * i + q;
+      const int a = init ? x : x + r;
+      const int b = init ? x : x - r - 1;
+      R.enter[i] = ld(clamp_pos(a));
+      R.leave[i] = ld(clamp_pos(b));
+    }
+    const int x = clamp_pos(base + (lane & (kChunk - 1)));
+    const int hi = x + r < w - 1 ? x + r : w - 1;
+    const int lo = x - r > 0 ? x - r : 0;
+    R.mult = inv[hi - lo + 1];
+  }
+
+  __device__ __forceinline__ void stage(const StagedRegs<S>& R) const {
 #pragma unroll
-      for (int i = 0; i < Shape::kVec; ++i) {
-        const int x = x0 + Shape::kPos * i + q;
-        const int a = x + r, b = x - r - 1;
-        R.enter[i] = (x < w && a <= w - 1) ? ld(a) : zero;
-        R.leave[i] = (x < w && b >= 0) ? ld(b) : zero;
-      }
-      const int x = x0 + (lane & (kStageChunk - 1));
-      const int hi = x + r < w - 1 ? x + r : w - 1;
-      const int lo = x - r > 0 ? x - r : 0;
-      R.mult = x < w ? inv[hi - lo + 1] : 0.0f;
+    for (int i = 0; i < Shape::kVec; ++i) {
+      *reinterpret_cast<uint4*>(&lds->enter[Shape::kPos * i + q][Shape::kChannels * j]) = R.enter[i];
+      *reinterpret_cast<uint4*>(&lds->leave[Shape::kPos * i + q][Shape::kChannels * j]) = R.leave[i];
     }
   }
 
-  // Output positions x0 .. x0 + kStageChunk - 1, all inside the grid, all
-  // with (ENTER) or without an entering value and all with (LEAVE) or
-  // without a leaving one: no per-position tests.
+  // Output positions x0 .. x0 + kStageSub - 1 (LDS rows p0 ..), all inside
+  // the grid, all with (ENTER) or without an entering value and all with
+  // (LEAVE) or without a leaving one: no per-position tests.
   template <bool ENTER, bool LEAVE>
-  __device__ __forceinline__ void run_uniform(int mult_bits, float& s) const {
-    float e[kStageChunk], l[kStageChunk];
+  __device__ __forceinline__ void run_uniform(int p0, int mult_bits, float& s) const {
+    float e[kStageSub], l[kStageSub];
 #pragma unroll
-    for (int p = 0; p < kStageChunk; ++p) {
-      if (ENTER) e[p] = s_enter[p][lane];
-      if (LEAVE) l[p] = s_leave[p][lane];
+    for (int p = 0; p < kStageSub; ++p) {
+      if (ENTER) e[p] = Storage<S>::widen(lds->enter[p0 + p][lane]);
+      if (LEAVE) l[p] = Storage<S>::widen(lds->leave[p0 + p][lane]);
     }
 #pragma unroll
-    for (int p = 0; p < kStageChunk; ++p) {
+    for (int p = 0; p < kStageSub; ++p) {
       if (ENTER) s = s + e[p];
       if (LEAVE) s = s - l[p];
-      s_out[p][lane] = s * __int_as_float(__builtin_amdgcn_readlane(mult_bits, p));
+      lds->out[p0 + p][lane] =
+          Storage<S>::narrow(s * __int_as_float(__builtin_amdgcn_readlane(mult_bits, p0 + p)));
     }
   }
 
-  // Any chunk: the tests of each position select the update.
-  __device__ __forceinline__ void run_mixed(int x0, int mult_bits, float& s) const {
-    float e[kStageChunk], l[kStageChunk];
+  // Any positions: the tests of each position select the update.
+  __device__ __forceinline__ void run_mixed(int x0, int p0, int mult_bits, float& s) const {
+    float e[kStageSub], l[kStageSub];
 #pragma unroll
-    for (int p = 0; p < kStageChunk; ++p) {
-      e[p] = s_enter[p][lane];
-      l[p] = s_leave[p][lane];
+    for (int p = 0; p < kStageSub; ++p) {
+      e[p] = Storage<S>::widen(lds->enter[p0 + p][lane]);
+      l[p] = Storage<S>::widen(lds->leave[p0 + p][lane]);
     }
 #pragma unroll
-    for (int p = 0; p < kStageChunk; ++p) {
+    for (int p = 0; p < kStageSub; ++p) {
       const int x = x0 + p;
       const bool inside = x < w;
       const float with_enter = s + e[p];
       s = (inside && x + r <= w - 1) ? with_enter : s;
       const float with_leave = s - l[p];
       s = (inside && x - r - 1 >= 0) ? with_leave : s;
-      s_out[p][lane] = s * __int_as_float(__builtin_amdgcn_readlane(mult_bits, p));
+      lds->out[p0 + p][lane] =
+          Storage<S>::narrow(s * __int_as_float(__builtin_amdgcn_readlane(mult_bits, p0 + p)));
     }
   }
 
-  // Lanes exchange the staged values through LDS. DS instructions of one
-  // wave execute in issue order, and every LDS read below may alias an
-  // earlier LDS write in the compiler's view, so program order suffices.
-  __device__ __forceinline__ void consume(int c, const StagedRegs<S>& R, float& s) const {
-#pragma unroll
-    for (int i = 0; i < Shape::kVec; ++i) {
-      stage_in(&s_enter[Shape::kPos * i + q][Shape::kChannels * j], R.enter[i], S());
-      stage_in(&s_leave[Shape::kPos * i + q][Shape::kChannels * j], R.leave[i], S());
-    }
+  // Sum chunk c from LDS and store its outputs. DS instructions of one wave
+  // execute in issue order, and every LDS read below may alias an earlier
+  // LDS write in the compiler's view, so program order suffices.
+  __device__ __forceinline__ void consume(int c, int mult_bits, float& s) const {
     if (c < n_init) {
-      const int t0 = c * kStageChunk;
-      float e[kStageChunk];
 #pragma unroll
-      for (int p = 0; p < kStageChunk; ++p) e[p] = s_enter[p][lane];
-      if (t0 > 0 && t0 + kStageChunk - 1 <= first_hi) {
+      for (int p0 = 0; p0 < kChunk; p0 += kStageSub) {
+        const int t0 = c * kChunk + p0;
+        float e[kStageSub];
 #pragma unroll
-        for (int p = 0; p < kStageChunk; ++p) s = s + e[p];
-      } else {
+        for (int p = 0; p < kStageSub; ++p) e[p] = Storage<S>::widen(lds->enter[p0 + p][lane]);
+        if (t0 > 0 && t0 + kStageSub - 1 <= first_hi) {
 #pragma unroll
-        for (int p = 0; p < kStageChunk; ++p) {
-          const int t = t0 + p;
-          const float added = t == 0 ? e[p] : s + e[p];
-          s = t <= first_hi ? added : s;
+          for (int p = 0; p < kStageSub; ++p) s = s + e[p];
+        } else {
+#pragma unroll
+          for (int p = 0; p < kStageSub; ++p) {
+            const int t = t0 + p;
+            const float added = t == 0 ? e[p] : s + e[p];
+            s = t <= first_hi ? added : s;
+          }
         }
       }
       if (c == n_init - 1) dst[lane] = Storage<S>::narrow(s * inv[first_hi + 1]);
       return;
     }
-    const int x0 = 1 + (c - n_init) * kStageChunk;
-    const int x1 = x0 + kStageChunk - 1;
-    const int mult_bits = __float_as_int(R.mult);
-    // Position x has an entering value iff x + r <= w - 1 and a leaving
-    // value iff x - r - 1 >= 0.
-    const bool all_in = x1 < w;
-    const bool enter_all = x1 + r <= w - 1, enter_none = x0 + r > w - 1;
-    const bool leave_all = x0 - r - 1 >= 0, leave_none = x1 - r - 1 < 0;
-    if (all_in && enter_all && leave_all)
-      run_uniform<true, true>(mult_bits, s);
-    else if (all_in && enter_all && leave_none)
-      run_uniform<true, false>(mult_bits, s);
-    else if (all_in && enter_none && leave_all)
-      run_uniform<false, true>(mult_bits, s);
-    else if (all_in && enter_none && leave_none)
-      run_uniform<false, false>(mult_bits, s);
-    else
-      run_mixed(x0, mult_bits, s);
+    const int x0c = 1 + (c - n_init) * kChunk;
+#pragma unroll
+    for (int p0 = 0; p0 < kChunk; p0 += kStageSub) {
+      const int x0 = x0c + p0;
+      const int x1 = x0 + kStageSub - 1;
+      // Position x has an entering value iff x + r <= w - 1 and a leaving
+      // value iff x - r - 1 >= 0.
+      const bool all_in = x1 < w;
+      const bool enter_all = x1 + r <= w - 1, enter_none = x0 + r > w - 1;
+      const bool leave_all = x0 - r - 1 >= 0, leave_none = x1 - r - 1 < 0;
+      if (all_in && enter_all && leave_all)
+        run_uniform<true, true>(p0, mult_bits, s);
+      else if (all_in && enter_all && leave_none)
+        run_uniform<true, false>(p0, mult_bits, s);
+      else if (all_in && enter_none && leave_all)
+        run_uniform<false, true>(p0, mult_bits, s);
+      else if (all_in && enter_none && leave_none)
+        run_uniform<false, false>(p0, mult_bits, s);
+      else
+        run_mixed(x0, p0, mult_bits, s);
+    }
 #pragma unroll
     for (int i = 0; i < Shape::kVec; ++i) {
-      const int x = x0 + Shape::kPos * i + q;
+      const int x = x0c + Shape::kPos * i + q;
       if (x < w)
         reinterpret_cast<uint4*>(dst + static_cast<int64_t>(x) * step)[j] =
-            stage_out(&s_out[Shape::kPos * i + q][Shape::kChannels * j], S());
+            *reinterpret_cast<const uint4*>(&lds->out[Shape::kPos * i + q][Shape::kChannels * j]);
     }
   }
 };
@@ -571,7 +574,7 @@ struct StagedLine {
 template <typename S>
 __device__ __forceinline__ void blur_staged_line(const S* __restrict__ in, S* __restrict__ out, int w, int r,
                                                  int vertical, const float* __restrict__ inv, int64_t line,
-                                                 int lane, float (*stage)[kStageChunk][64]) {
+                                                 int lane, StagedLds<S>* lds) {
   StagedLine<S> L;
   const int64_t base = vertical ? line * 64 : line * w * 64;
   L.src = in + base;
@@ -583,60 +586,59 @@ __device__ __forceinline__ void blur_staged_line(const S* __restrict__ in, S* __
   L.q = lane / StagedShape<S>::kLanesPerCell;
   L.j = lane % StagedShape<S>::kLanesPerCell;
   L.lane = lane;
-  L.s_enter = stage[0];
-  L.s_leave = stage[1];
-  L.s_out = stage[2];
+  L.lds = lds;
   if (r == 0) {
     for (int x = 0; x < w; ++x) L.dst[x * L.step + lane] = L.src[x * L.step + lane];
     return;
   }
+  constexpr int kChunk = StagedShape<S>::kChunk;
   L.first_hi = r < w - 1 ? r : w - 1;
-  L.n_init = (L.first_hi + kStageChunk) / kStageChunk;
-  const int n_chunks = L.n_init + (w - 1 + kStageChunk - 1) / kStageChunk;
-  // A ring of kStageDepth register chunks: chunk c + kStageDepth - 1 is
-  // requested before chunk c is summed.
+  L.n_init = (L.first_hi + kChunk) / kChunk;
+  L.n_chunks = L.n_init + (w - 1 + kChunk - 1) / kChunk;
   float s = 0.0f;
-  StagedRegs<S> ring[kStageDepth];
-#pragma unroll
-  for (int b = 0; b < kStageDepth - 1; ++b)
-    if (b < n_chunks) L.fetch(b, ring[b]);
-  for (int c0 = 0; c0 < n_chunks; c0 += kStageDepth) {
-#pragma unroll
-    for (int b = 0; b < kStageDepth; ++b) {
-      const int c = c0 + b;
-      if (c >= n_chunks) break;
-      const int ahead = c + kStageDepth - 1;
-      if (ahead < n_chunks) L.fetch(ahead, ring[(b + kStageDepth - 1) % kStageDepth]);
-      L.consume(c, ring[b], s);
-    }
+  StagedRegs<S> R;
+  L.fetch(0, R);
+  for (int c = 0; c < L.n_chunks; ++c) {
+    L.stage(R);
+    const int mult_bits = __float_as_int(R.mult);
+    if (c + 1 < L.n_chunks) L.fetch(c + 1, R);
+    L.consume(c, mult_bits, s);
   }
 }
 
-// One wave per line; a launch of fewer waves than lines walks the lines
-// with a stride.
-template <typename S>
-__global__ __launch_bounds__(kBlock) void k_blur_staged64(const S* __restrict__ in, S* __restrict__ out, int w,
-                                                          const DevState* __restrict__ st, int radius,
-                                                          int vertical, const float* __restrict__ inv) {
-  __shared__ float s_stage[kWavesPerBlock][3][kStageChunk][64];
-  if (st != nullptr && st->done) return;
-  const int r = st != nullptr ? st->r : radius;
+// One wave per line, WPB waves per block: block `bid` of `nblocks` takes
+// lines bid * WPB + wave, and walks on with a stride if there are more lines
+// than waves.
+template <typename S, int WPB>
+__device__ __forceinline__ void blur_staged_lines(const S* __restrict__ in, S* __restrict__ out, int w, int r,
+                                                  int vertical, const float* __restrict__ inv, int64_t bid,
+                                                  int64_t nblocks, StagedLds<S>* stage) {
   const int wib = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  for (int64_t line = static_cast<int64_t>(blockIdx.x) * kWavesPerBlock + wib; line < w;
-       line += static_cast<int64_t>(gridDim.x) * kWavesPerBlock)
-    blur_staged_line<S>(in, out, w, r, vertical, inv, line, lane, s_stage[wib]);
+  for (int64_t line = bid * WPB + wib; line < w; line += nblocks * WPB)
+    blur_staged_line<S>(in, out, w, r, vertical, inv, line, lane, stage + wib);
+}
+
+template <typename S, int WPB>
+__global__ __launch_bounds__(WPB * 64) void k_blur_staged64(const S* __restrict__ in, S* __restrict__ out, int w,
+                                                            const DevState* __restrict__ st, int radius,
+                                                            int vertical, const float* __restrict__ inv) {
+  __shared__ StagedLds<S> s_stage[WPB];
+  if (st != nullptr && st->done) return;
+  const int r = st != nullptr ? st->r : radius;
+  blur_staged_lines<S, WPB>(in, out, w, r, vertical, inv, blockIdx.x, gridDim.x, s_stage);
 }
 
 // ---------------------------------------------------------- group table
 
 // table[t] = pi(t) packed as (ly << 16) | lx, pi the grouping bijection of
 // a reorder over the beta^2 block-local cells, filled by all blocks.
-__device__ __forceinline__ void fill_group_table(int32_t* __restrict__ table, int beta, const uint64_t keys[4]) {
+__device__ __forceinline__ void fill_group_table(int32_t* __restrict__ table, int beta, const uint64_t keys[4],
+                                                 int64_t bid, int64_t nblocks) {
   const uint64_t cells = static_cast<uint64_t>(beta) * beta;
   const Bijection f(cells, keys);
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kBlock;
-  for (uint64_t t = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; t < cells; t += stride) {
+  const uint64_t stride = static_cast<uint64_t>(nblocks) * kBlock;
+  for (uint64_t t = static_cast<uint64_t>(bid) * kBlock + threadIdx.x; t < cells; t += stride) {
     const uint32_t v = static_cast<uint32_t>(f(t));
     const uint32_t ly = v / static_cast<uint32_t>(beta);
     const uint32_t lx = v - ly * static_cast<uint32_t>(beta);
@@ -647,7 +649,7 @@ __device__ __forceinline__ void fill_group_table(int32_t* __restrict__ table, in
 __global__ __launch_bounds__(kBlock) void k_group_table(int32_t* __restrict__ table,
                                                         const DevState* __restrict__ st) {
   if (st->done) return;
-  fill_group_table(table, st->beta, st->keys);
+  fill_group_table(table, st->beta, st->keys, blockIdx.x, gridDim.x);
 }
 
 // Squared distance partial over one lane's 4 channels, as the two lowest
@@ -848,12 +850,11 @@ __device__ __forceinline__ void argmin_level(unsigned long long& best, int& best
   }
 }
 
+// Block `bid` of `nblocks` blocks that share one reorder's items.
 template <int DP, typename S>
-__global__ __launch_bounds__(kBlock) void k_assign(S* __restrict__ G, const S* __restrict__ T,
-                                                   int32_t* __restrict__ P,
-                                                   const int32_t* __restrict__ table,
-                                                   DevState* __restrict__ st) {
-  if (st->done) return;
+__device__ __forceinline__ void assign_items(S* __restrict__ G, const S* __restrict__ T, int32_t* __restrict__ P,
+                                             const int32_t* __restrict__ table, DevState* __restrict__ st,
+                                             int64_t bid, int64_t nblocks) {
   constexpr int LG = DP / 4;
   constexpr int IPW = 64 / LG;
   constexpr int LEVELS = LG == 1 ? 0 : LG == 2 ? 1 : LG == 4 ? 2 : LG == 8 ? 3 : 4;
@@ -866,8 +867,8 @@ __global__ __launch_bounds__(kBlock) void k_assign(S* __restrict__ G, const S* _
   const int wib = threadIdx.x >> 6;
   const int sub = lane % LG, slot = lane / LG;
   unsigned long long* q_item = s_q[wib][slot];
-  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 6;
-  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * kBlock) >> 6;
+  const int64_t wave = (bid * kBlock + threadIdx.x) >> 6;
+  const int64_t nwaves = (nblocks * kBlock) >> 6;
   using Quad = typename Storage<S>::Quad;
   const Quad* __restrict__ G4 = reinterpret_cast<const Quad*>(G);
   const Quad* __restrict__ T4 = reinterpret_cast<const Quad*>(T);
@@ -981,10 +982,19 @@ __global__ __launch_bounds__(kBlock) void k_assign(S* __restrict__ G, const S* _
       e += s_sum[0][i];
       m += s_sum[1][i];
     }
-    const int slot_acc = static_cast<int>(blockIdx.x % kAccSlots);
+    const int slot_acc = static_cast<int>(bid % kAccSlots);
     atomicAdd(&st->energy_acc[slot_acc], e);
     atomicAdd(&st->moved_acc[slot_acc], m);
   }
+}
+
+template <int DP, typename S>
+__global__ __launch_bounds__(kBlock) void k_assign(S* __restrict__ G, const S* __restrict__ T,
+                                                   int32_t* __restrict__ P,
+                                                   const int32_t* __restrict__ table,
+                                                   DevState* __restrict__ st) {
+  if (st->done) return;
+  assign_items<DP, S>(G, T, P, table, st, blockIdx.x, gridDim.x);
 }
 
 // ----------------------------------------------------------------- energy
@@ -1089,18 +1099,17 @@ __device__ void control_step(DevState& st, const LevelInfo* __restrict__ levels,
 // every block reads `in` (nothing writes it during this launch) and applies
 // the same control step to its own LDS copy, so all blocks agree on the next
 // beta and keys; block 0 alone writes `out` and the trace.
-__global__ __launch_bounds__(kBlock) void k_step(const DevState* __restrict__ in, DevState* __restrict__ out,
-                                                 const LevelInfo* __restrict__ levels,
-                                                 plas_level_out* __restrict__ trace,
-                                                 int32_t* __restrict__ table) {
+__device__ __forceinline__ void step_body(const DevState* __restrict__ in, DevState* __restrict__ out,
+                                          const LevelInfo* __restrict__ levels, plas_level_out* __restrict__ trace,
+                                          int32_t* __restrict__ table, int64_t bid, int64_t nblocks,
+                                          DevState& s_st) {
   static_assert(sizeof(DevState) % 4 == 0, "state is copied as 32-bit words");
   constexpr int kWords = sizeof(DevState) / 4;
-  __shared__ DevState s_st;
   uint32_t* words = reinterpret_cast<uint32_t*>(&s_st);
   for (int i = threadIdx.x; i < kWords; i += kBlock) words[i] = reinterpret_cast<const uint32_t*>(in)[i];
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (!s_st.done && s_st.pending) control_step(s_st, levels, blockIdx.x == 0 ? trace : nullptr);
+    if (!s_st.done && s_st.pending) control_step(s_st, levels, bid == 0 ? trace : nullptr);
     s_st.pending = 1;
     for (int i = 0; i < kAccSlots; ++i) {
       s_st.energy_acc[i] = 0;
@@ -1108,10 +1117,129 @@ __global__ __launch_bounds__(kBlock) void k_step(const DevState* __restrict__ in
     }
   }
   __syncthreads();
-  if (blockIdx.x == 0)
+  if (bid == 0)
     for (int i = threadIdx.x; i < kWords; i += kBlock) reinterpret_cast<uint32_t*>(out)[i] = words[i];
   if (s_st.done) return;
-  fill_group_table(table, s_st.beta, s_st.keys);
+  fill_group_table(table, s_st.beta, s_st.keys, bid, nblocks);
+}
+
+__global__ __launch_bounds__(kBlock) void k_step(const DevState* __restrict__ in, DevState* __restrict__ out,
+                                                 const LevelInfo* __restrict__ levels,
+                                                 plas_level_out* __restrict__ trace,
+                                                 int32_t* __restrict__ table) {
+  __shared__ DevState s_st;
+  step_body(in, out, levels, trace, table, blockIdx.x, gridDim.x, s_st);
+}
+
+// ------------------------------------------------------------------ batch
+//
+// Many independent sorts advance together, one reorder per launch sequence.
+// grids[i] holds sort i's buffers and state pair; a launch covers several
+// sorts, and its block map gives each block its sort and its index among
+// that sort's blocks: map[b] = (grid index << 16) | block index. Every block
+// then runs exactly the code of a single-sort launch of that sort's shape,
+// so each sort's result does not depend on the batch it runs in.
+
+// The kernels' view of BatchGrid: the same layout, with every pointer
+// declared as device (global) memory. Pointers read from memory are
+// otherwise generic to the compiler, which then emits flat instructions.
+#define PLAS_GLOBAL __attribute__((address_space(1)))
+struct BatchGridView {
+  void PLAS_GLOBAL* G;
+  void PLAS_GLOBAL* H;
+  void PLAS_GLOBAL* T;
+  int32_t PLAS_GLOBAL* P;
+  int32_t PLAS_GLOBAL* table;
+  const float PLAS_GLOBAL* inv;
+  const LevelInfo PLAS_GLOBAL* levels;
+  plas_level_out PLAS_GLOBAL* trace;
+  DevState PLAS_GLOBAL* states;
+  int32_t w;
+  int32_t step_blocks;
+  int32_t blur_blocks;
+  int32_t assign_blocks;
+};
+static_assert(sizeof(BatchGridView) == sizeof(BatchGrid), "descriptor view layout");
+static_assert(offsetof(BatchGridView, w) == offsetof(BatchGrid, w), "descriptor view layout");
+
+__device__ __forceinline__ const BatchGridView& batch_grid(const BatchGrid* __restrict__ grids,
+                                                           const uint32_t* __restrict__ map, uint32_t& local) {
+  const uint32_t e = map[blockIdx.x];
+  local = e & 0xffffu;
+  return reinterpret_cast<const BatchGridView*>(grids)[e >> 16];
+}
+
+// A global pointer of the view as a plain pointer of type T (the compiler
+// keeps track of where it points).
+template <typename T, typename U>
+__device__ __forceinline__ T* global_ptr(U PLAS_GLOBAL* p) {
+  return (T*)((T PLAS_GLOBAL*)p);
+}
+
+__global__ __launch_bounds__(kBlock) void k_step_batch(const BatchGrid* __restrict__ grids,
+                                                       const uint32_t* __restrict__ map, int src) {
+  __shared__ DevState s_st;
+  uint32_t local;
+  const BatchGridView& g = batch_grid(grids, map, local);
+  DevState* states = global_ptr<DevState>(g.states);
+  step_body(states + src, states + (src ^ 1), global_ptr<const LevelInfo>(g.levels),
+            global_ptr<plas_level_out>(g.trace), global_ptr<int32_t>(g.table), local, g.step_blocks, s_st);
+}
+
+template <typename S, int WPB>
+__global__ __launch_bounds__(WPB * 64) void k_blur_staged64_batch(const BatchGrid* __restrict__ grids,
+                                                                  const uint32_t* __restrict__ map,
+                                                                  int state_idx, int vertical) {
+  __shared__ StagedLds<S> s_stage[WPB];
+  uint32_t local;
+  const BatchGridView& g = batch_grid(grids, map, local);
+  const DevState* st = global_ptr<const DevState>(g.states) + state_idx;
+  if (st->done) return;
+  const S* in = global_ptr<const S>(vertical ? g.H : g.G);
+  S* out = global_ptr<S>(vertical ? g.T : g.H);
+  blur_staged_lines<S, WPB>(in, out, g.w, st->r, vertical, global_ptr<const float>(g.inv), local, g.blur_blocks,
+                            s_stage);
+}
+
+template <int DP, typename S>
+__global__ __launch_bounds__(kBlock) void k_blur_batch(const BatchGrid* __restrict__ grids,
+                                                       const uint32_t* __restrict__ map, int state_idx,
+                                                       int vertical) {
+  uint32_t local;
+  const BatchGridView& g = batch_grid(grids, map, local);
+  const DevState* st = global_ptr<const DevState>(g.states) + state_idx;
+  if (st->done) return;
+  const S* in = global_ptr<const S>(vertical ? g.H : g.G);
+  S* out = global_ptr<S>(vertical ? g.T : g.H);
+  const int64_t wave = (static_cast<int64_t>(local) * kBlock + threadIdx.x) >> 6;
+  blur_reg_lines<DP, S>(in, out, g.w, st->r, vertical, global_ptr<const float>(g.inv), wave, threadIdx.x & 63);
+}
+
+template <int DP, typename S>
+__global__ __launch_bounds__(kBlock) void k_assign_batch(const BatchGrid* __restrict__ grids,
+                                                         const uint32_t* __restrict__ map, int state_idx) {
+  uint32_t local;
+  const BatchGridView& g = batch_grid(grids, map, local);
+  DevState* st = global_ptr<DevState>(g.states) + state_idx;
+  if (st->done) return;
+  assign_items<DP, S>(global_ptr<S>(g.G), global_ptr<const S>(g.T), global_ptr<int32_t>(g.P),
+                      global_ptr<const int32_t>(g.table), st, local, g.assign_blocks);
+}
+
+// (done, k) of each listed sort's state `state_idx`, for the host's check
+// between chunks.
+__global__ __launch_bounds__(kBlock) void k_batch_status(const BatchGrid* __restrict__ grids,
+                                                         const int32_t* __restrict__ list, int count,
+                                                         int state_idx, HostStatus* __restrict__ out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= count) return;
+  const DevState* st =
+      global_ptr<const DevState>(reinterpret_cast<const BatchGridView*>(grids)[list[i]].states) + state_idx;
+  HostStatus hs;
+  hs.done = st->done;
+  hs.pad = 0;
+  hs.k = st->k;
+  out[i] = hs;
 }
 
 }  // namespace
@@ -1211,13 +1339,13 @@ hipError_t launch_blur_pass(const void* in, void* out, int w, int dp, int storag
     const int lines_per_block = kWavesPerBlock * PLAS_BLUR_LINES_PER_WAVE;
     const int blocks = (w + lines_per_block - 1) / lines_per_block;
     PLAS_DISPATCH_STORAGE(storage, {
-      k_blur_staged64<SV><<<blocks, kBlock, 0, stream>>>(static_cast<const SV*>(in), static_cast<SV*>(out), w,
-                                                         st, radius, vertical, inv);
+      k_blur_staged64<SV, kWavesPerBlock><<<blocks, kBlock, 0, stream>>>(
+          static_cast<const SV*>(in), static_cast<SV*>(out), w, st, radius, vertical, inv);
     });
     return hipGetLastError();
   }
-  const int lines_per_wave = 64 / dp;
-  const int64_t waves = (w + lines_per_wave - 1) / lines_per_wave;
+  int64_t waves = 0;
+  PLAS_DISPATCH_DP(dp, waves = blur_reg_waves<DPV>(w));
   const int blocks = static_cast<int>((waves + kWavesPerBlock - 1) / kWavesPerBlock);
   PLAS_DISPATCH_STORAGE(storage, {
     PLAS_DISPATCH_DP(dp, (k_blur<DPV, SV><<<blocks, kBlock, 0, stream>>>(
@@ -1260,6 +1388,77 @@ hipError_t launch_energy(const void* G, const void* T, int64_t n, int dp, int st
     PLAS_DISPATCH_DP(dp, (k_energy<DPV, SV><<<blocks, kBlock, 0, stream>>>(
                              static_cast<const SV*>(G), static_cast<const SV*>(T), n, scale, energy_out)));
   });
+  return hipGetLastError();
+}
+
+// ---- batch
+
+int batch_step_blocks(int64_t max_cells) { return blocks_for(max_cells, 1024); }
+
+int batch_blur_blocks(int w, int dp, int waves_per_block) {
+  if (dp == 64) return (w + waves_per_block - 1) / waves_per_block;
+  int64_t waves = 0;
+  switch (dp) {
+    case 4: waves = blur_reg_waves<4>(w); break;
+    case 8: waves = blur_reg_waves<8>(w); break;
+    case 16: waves = blur_reg_waves<16>(w); break;
+    default: waves = blur_reg_waves<32>(w); break;
+  }
+  return static_cast<int>((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+}
+
+int batch_assign_blocks(int64_t max_items, int dp, int cap) {
+  const int64_t items_per_wave = 64 / (dp / 4);
+  const int64_t waves = (max_items + items_per_wave - 1) / items_per_wave;
+  return blocks_for(waves * 64, cap > 0 ? cap : PLAS_ASSIGN_MAX_BLOCKS);
+}
+
+int default_assign_blocks_cap() { return PLAS_ASSIGN_MAX_BLOCKS; }
+
+hipError_t launch_step_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int src,
+                             hipStream_t stream) {
+  k_step_batch<<<blocks, kBlock, 0, stream>>>(grids, map, src);
+  return hipGetLastError();
+}
+
+hipError_t launch_blur_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
+                             int waves_per_block, int state_idx, int vertical, hipStream_t stream) {
+  if (dp == 64) {
+    PLAS_DISPATCH_STORAGE(storage, {
+      switch (waves_per_block) {
+        case 1:
+          k_blur_staged64_batch<SV, 1><<<blocks, 64, 0, stream>>>(grids, map, state_idx, vertical);
+          break;
+        case 2:
+          k_blur_staged64_batch<SV, 2><<<blocks, 128, 0, stream>>>(grids, map, state_idx, vertical);
+          break;
+        case 4:
+          k_blur_staged64_batch<SV, 4><<<blocks, 256, 0, stream>>>(grids, map, state_idx, vertical);
+          break;
+        default:
+          return hipErrorInvalidValue;
+      }
+    });
+    return hipGetLastError();
+  }
+  PLAS_DISPATCH_STORAGE(storage, {
+    PLAS_DISPATCH_DP(dp, (k_blur_batch<DPV, SV><<<blocks, kBlock, 0, stream>>>(grids, map, state_idx, vertical)));
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_assign_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
+                               int state_idx, hipStream_t stream) {
+  PLAS_DISPATCH_STORAGE(storage, {
+    PLAS_DISPATCH_DP(dp, (k_assign_batch<DPV, SV><<<blocks, kBlock, 0, stream>>>(grids, map, state_idx)));
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_status(const BatchGrid* grids, const int32_t* list, int count, int state_idx,
+                               HostStatus* out, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  k_batch_status<<<(count + kBlock - 1) / kBlock, kBlock, 0, stream>>>(grids, list, count, state_idx, out);
   return hipGetLastError();
 }
 

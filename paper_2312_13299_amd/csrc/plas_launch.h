@@ -59,6 +59,27 @@ hipError_t launch_assign(void* G, const void* T, int32_t* P, const int32_t* tabl
 // table of the next reorder. in and out are two different state buffers.
 hipError_t launch_step(const DevState* in, DevState* out, const LevelInfo* levels, plas_level_out* trace,
                        int32_t* table, int64_t max_cells, hipStream_t stream);
+// ---- batches of sorts (BatchGrid in plas_device.h). A launch's block map
+// (device uint32[blocks]) holds (grid index << 16) | block index within the
+// grid's blocks; a grid's entries run from 0 to its block count - 1.
+// Blocks each grid takes per launch kind.
+int batch_step_blocks(int64_t max_cells);
+int batch_blur_blocks(int w, int dp, int waves_per_block);  // waves_per_block: 1, 2, 4 (dp == 64 only)
+int batch_assign_blocks(int64_t max_items, int dp, int cap);  // cap <= 0: the single-sort default
+int default_assign_blocks_cap();
+// Step of every mapped grid: reads states[src], writes states[src ^ 1].
+hipError_t launch_step_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int src,
+                             hipStream_t stream);
+// One blur pass (vertical 0: G -> H, 1: H -> T) of every mapped grid, all of
+// dp channels and `storage`, with states[state_idx].
+hipError_t launch_blur_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
+                             int waves_per_block, int state_idx, int vertical, hipStream_t stream);
+hipError_t launch_assign_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
+                               int state_idx, hipStream_t stream);
+// out[i] = (done, k) of grids[list[i]].states[state_idx], i < count.
+hipError_t launch_batch_status(const BatchGrid* grids, const int32_t* list, int count, int state_idx,
+                               HostStatus* out, hipStream_t stream);
+
 // energy_out (device u64) += sum over cells of floor(d(G[p], T[p]) * 2^s).
 hipError_t launch_energy(const void* G, const void* T, int64_t n, int dp, int storage, int s,
                          unsigned long long* energy_out, hipStream_t stream);

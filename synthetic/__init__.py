@@ -35,6 +35,9 @@ DATA_SEED_SMALL = 1       # 64 x 64 grid
 DATA_SEED_SCENE = 2       # 1024 x 1024 grid
 DATA_SEED_PRECISION = 3   # 1448 x 1448 grid
 SORT_SEED = 0x5EED
+DATA_SEED_BATCH = 4       # the 64-grid batch: sides and per-grid data seeds
+BATCH_GRIDS = 64
+BATCH_SIDE_RANGE = (128, 724)
 
 
 def gaussian_attributes(n: int, seed: int, layout: str = "cn") -> np.ndarray:
@@ -115,3 +118,13 @@ def random_permutation(n: int, seed: int) -> np.ndarray:
     inputs in tests)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.permutation(n).astype(np.int32)
+
+
+def batch_workload(count: int = BATCH_GRIDS, lo: int = BATCH_SIDE_RANGE[0], hi: int = BATCH_SIDE_RANGE[1],
+                   seed: int = DATA_SEED_BATCH) -> list[tuple[int, int, int]]:
+    """The batch of independent grids: (side, data seed, sort seed) per grid,
+    sides log-uniform in [lo, hi]; grid i's features are
+    gaussian_attributes(side**2, data seed) and its sort seed is
+    SORT_SEED + i."""
+    sides = batched_sides(count, lo, hi, seed)
+    return [(side, seed * 1000 + i, SORT_SEED + i) for i, side in enumerate(sides)]

@@ -110,3 +110,52 @@ def test_null_handle_is_rejected(plas):
     stats.struct_size = ctypes.sizeof(stats)
     assert L.plas_sort(None, None, 4, 1, 2, 0, 0, None, None, ctypes.byref(stats)) == plas.ERR_INVALID_ARGUMENT
     assert L.plas_last_error(None) == b""
+
+
+def test_batch_structs_and_defaults(plas):
+    # plas_batch_item: 8 + 8 + 6*4 + 8 + 3 pointers; the config ends in a pointer.
+    assert ctypes.sizeof(plas.BatchItem) == 72
+    assert ctypes.sizeof(plas.TuneEntry) == 16
+    assert ctypes.sizeof(plas.BatchConfig) == 32
+    assert ctypes.sizeof(plas.BatchStats) == 88
+    c = plas.BatchConfig()
+    assert plas.library().plas_batch_config_init(ctypes.byref(c)) == 0
+    assert c.struct_size == ctypes.sizeof(plas.BatchConfig)
+    assert c.graph == 0 and c.reorders_per_sync == 0 and c.profile == 0 and c.tune_count == 0
+    assert plas.library().plas_batch_config_init(None) == plas.ERR_INVALID_ARGUMENT
+
+
+def test_batch_null_handle_is_rejected(plas):
+    L = plas.library()
+    items = (plas.BatchItem * 1)()
+    assert L.plas_sort_batch(None, items, 1, None, None, None) == plas.ERR_INVALID_ARGUMENT
+    table = (plas.TuneEntry * 4)()
+    n = ctypes.c_int32()
+    assert L.plas_autotune_batch(None, items, 1, None, 0, table, 4, ctypes.byref(n)) == plas.ERR_INVALID_ARGUMENT
+
+
+def test_job_footprint(plas):
+    # Three grids of n * dp elements dominate; the permutation, grouping table
+    # and small tables add about 4 bytes per cell plus the table of the
+    # largest block (beta = side/2 at the first level).
+    for side, d, storage, elem in ((256, 59, "f32", 4), (1024, 59, "bf16", 2), (100, 3, "f32", 4)):
+        n = side * side
+        dp = plas.padded_channels(d)
+        f = plas.job_footprint(side, d, storage)
+        beta = max(16, side // 2)
+        low = 3 * n * dp * elem + 4 * n + 4 * beta * beta
+        assert low <= f <= low + 64 * 1024
+    with pytest.raises(plas.PlasError):
+        plas.job_footprint(1, 59)
+    with pytest.raises(plas.PlasError):
+        plas.job_footprint(64, 65)
+
+
+def test_server_null_arguments(plas):
+    L = plas.library()
+    h = ctypes.c_void_p()
+    assert L.plas_server_create(None, None, None, 1 << 30, ctypes.byref(h)) == plas.ERR_INVALID_ARGUMENT
+    assert L.plas_server_destroy(None) == 0
+    assert L.plas_server_step(None, None, None) == plas.ERR_INVALID_ARGUMENT
+    n = ctypes.c_int32()
+    assert L.plas_server_poll(None, None, None, 0, ctypes.byref(n)) == plas.ERR_INVALID_ARGUMENT
