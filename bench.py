@@ -11,7 +11,18 @@ already resident in device memory. Prints one JSON line.
 working grids stored in bfloat16; the same input is also sorted in float32
 on the same GPU and both are reported.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scene|precision]
+"batch" workload: 64 independent grids, sides log-uniform in [128, 724]
+(sum N = 11,833,105), D = 59 float32, sorted together by plas_sort_batch
+with graph replay and a measured tuning table; a step is the whole batch.
+The same grids sorted one after another by plas_sort are reported beside it.
+
+"serve" workload: a Poisson stream (mean 20 jobs/s) of sort jobs, sides
+log-uniform in [256, 1024], D = 59, float32 or bfloat16 storage (50/50),
+served by a continuous-batching plas_server; latency percentiles and
+throughput of a finite trace, and of a second trace at 0.8 x the measured
+capacity.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scene|precision|batch|serve]
 """
 from __future__ import annotations
 
@@ -95,12 +106,171 @@ def cpu_baseline(F, side: int, seed: int, reorders_full: int, sample_reorders: i
     }
 
 
+def percentile(values, q: float) -> float:
+    """Nearest-rank percentile."""
+    import math
+    v = sorted(values)
+    return v[max(0, min(len(v) - 1, math.ceil(q / 100.0 * len(v)) - 1))]
+
+
+def run_batch_workload(args, torch, plas, synthetic) -> int:
+    work = synthetic.batch_workload()
+    sides = [w[0] for w in work]
+    seeds = [w[2] for w in work]
+    t0 = time.perf_counter()
+    feats = [torch.from_numpy(synthetic.gaussian_attributes(s * s, ds)).cuda() for s, ds, _ in work]
+    n_total = sum(s * s for s in sides)
+    d = feats[0].shape[0]
+    log(f"batch inputs: {len(work)} grids, sum N {n_total}, {time.perf_counter() - t0:.1f} s")
+    ctx = plas.Context(0)
+    tune = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tune = ctx.autotune_batch(feats, sides=sides, seeds=seeds, graph=True)
+        log(f"autotune: {len(tune)} buckets in {time.perf_counter() - t0:.1f} s: {tune}")
+    for i in range(args.warmup):
+        ctx.sort_batch(feats, sides=sides, seeds=seeds, graph=True, tune=tune, max_reorders=16)
+    # Per-kernel times: a profiled batch of the first 200 reorders (every
+    # sort still runs then), direct launches timed with HIP events.
+    prof_reorders = 200
+    _, _, bp = ctx.sort_batch(feats, sides=sides, seeds=seeds, tune=tune, profile=True,
+                              max_reorders=prof_reorders)
+    torch.cuda.synchronize()
+    results = None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        perms, results, b = ctx.sort_batch(feats, sides=sides, seeds=seeds, graph=True, tune=tune)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = n_total * args.steps / elapsed
+    log(f"batch: {elapsed / args.steps:.2f} s per batch, {b.graph_builds} graphs, {b.launches} launches")
+    # The same grids one after another through plas_sort.
+    t0 = time.perf_counter()
+    same = 0
+    for f, s, seed, perm, res in zip(feats, sides, seeds, perms, results):
+        p1, r1 = ctx.sort(f, s, seed)
+        same += int(torch.equal(p1, perm) and r1.reorders == res.reorders and r1.energy_fixed == res.energy_fixed)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    blur_bytes = n_total * 2 * d * 4
+    blur_avg = bp.blur_ms / (2 * prof_reorders)
+    assign_avg = bp.assign_ms / prof_reorders
+    line = {
+        "metric": "Gaussians sorted/s, 64-grid batch D=59",
+        "value": round(value, 1), "unit": "Gaussians/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "plas_sort_batch_64_grids_128_724_d59_f32", "grids": len(work),
+                   "sum_n": n_total, "d": d, "side_min": min(sides), "side_max": max(sides),
+                   "graph": True, "tune": tune,
+                   "reorders_min": min(r.reorders for r in results),
+                   "reorders_max": max(r.reorders for r in results)},
+        "vs_single_sorts": {"value": round(n_total / t_plain, 1), "seconds": round(t_plain, 3),
+                            "speedup": round(t_plain / (elapsed / args.steps), 3),
+                            "identical": f"{same}/{len(work)}"},
+        "roofline": {
+            "bound": "hbm", "kernel": "blur_pass (batched, all 64 grids)",
+            "achieved": round(blur_bytes / (blur_avg * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(blur_bytes / (blur_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+            "per_launch_bytes": blur_bytes, "avg_launch_ms": round(blur_avg, 5),
+            "sample": f"first {prof_reorders} reorders of the batch, direct launches timed with HIP events",
+            "assign_avg_ms": round(assign_avg, 5), "step_avg_ms": round(bp.step_ms / prof_reorders, 5),
+        },
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def run_serve_workload(args, torch, plas, synthetic) -> int:
+    import numpy as np
+    ctx = plas.Context(0)
+    d = 59
+
+    def make_trace(count, rate, seed):
+        rng = np.random.Generator(np.random.PCG64(seed))
+        gaps = rng.exponential(1.0 / rate, size=count)
+        arrivals = np.cumsum(gaps) - gaps[0]
+        sides = synthetic.batched_sides(count, 256, 1024, seed + 1)
+        storages = ["f32" if v < 0.5 else "bf16" for v in rng.uniform(size=count)]
+        feats = [torch.from_numpy(synthetic.gaussian_attributes(s * s, seed * 1000 + i)).cuda()
+                 for i, s in enumerate(sides)]
+        return [dict(arrival=float(a), side=s, storage=st, features=f, seed=synthetic.SORT_SEED + i)
+                for i, (a, s, st, f) in enumerate(zip(arrivals, sides, storages, feats))]
+
+    def serve(trace, budget):
+        srv = plas.Server(ctx, budget, graph=True)
+        pending = sorted(trace, key=lambda j: j["arrival"])
+        ids = {}
+        finish = {}
+        max_running = 0
+        t0 = time.perf_counter()
+        nxt = 0
+        while len(finish) < len(trace):
+            now = time.perf_counter() - t0
+            while nxt < len(pending) and pending[nxt]["arrival"] <= now:
+                j = pending[nxt]
+                ids[srv.submit(j["features"], j["side"], j["seed"], storage=j["storage"])] = nxt
+                nxt += 1
+            running, waiting = srv.step()
+            max_running = max(max_running, running)
+            for job, status, perm, res in srv.poll():
+                if status != plas.OK:
+                    raise RuntimeError(f"job {job} failed with status {status}")
+                finish[ids[job]] = time.perf_counter() - t0
+            if running == 0 and waiting == 0 and nxt < len(pending):
+                time.sleep(max(0.0, pending[nxt]["arrival"] - (time.perf_counter() - t0)))
+        srv.close()
+        lat = [finish[i] - pending[i]["arrival"] for i in range(len(pending))]
+        n = sum(j["side"] ** 2 for j in pending)
+        makespan = max(finish.values()) - pending[0]["arrival"]
+        return dict(jobs=len(pending), p50_ms=round(percentile(lat, 50) * 1e3, 1),
+                    p99_ms=round(percentile(lat, 99) * 1e3, 1), max_ms=round(max(lat) * 1e3, 1),
+                    gaussians_per_s=round(n / makespan, 1), makespan_s=round(makespan, 3),
+                    offered_jobs_per_s=round(len(pending) / max(pending[-1]["arrival"], 1e-9), 2),
+                    max_running=max_running, sum_n=n)
+
+    budget = 64 << 30
+    t0 = time.perf_counter()
+    trace = make_trace(args.jobs, 20.0, 11)
+    log(f"trace 1: {args.jobs} jobs generated in {time.perf_counter() - t0:.1f} s")
+    # Warm-up: one small served job.
+    warm = make_trace(1, 20.0, 99)
+    serve(warm, budget)
+    r1 = serve(trace, budget)
+    log(f"trace 1 (20 jobs/s): {r1}")
+    mean_n = np.mean([j["side"] ** 2 for j in trace])
+    rate2 = 0.8 * r1["gaussians_per_s"] / mean_n
+    del trace
+    torch.cuda.empty_cache()
+    trace2 = make_trace(args.jobs, rate2, 12)
+    r2 = serve(trace2, budget)
+    log(f"trace 2 ({rate2:.2f} jobs/s): {r2}")
+    line = {
+        "metric": "served p50/p99 latency and Gaussians/s, Poisson 20 jobs/s, sides 256..1024, D=59",
+        "value": r1["gaussians_per_s"], "unit": "Gaussians/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": round(r1["makespan_s"] * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 or bf16 storage (50/50), f32 arithmetic", "data": "synthetic",
+        "config": {"workload": "plas_server_poisson_20_sides_256_1024_d59", "jobs": args.jobs,
+                   "memory_budget_bytes": budget, "graph": True},
+        "p50_ms": r1["p50_ms"], "p99_ms": r1["p99_ms"],
+        "trace_20_per_s": r1,
+        "trace_0p8_capacity": dict(r2, rate_jobs_per_s=round(rate2, 3)),
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("scene", "precision"), default="scene")
+    ap.add_argument("--workload", choices=("scene", "precision", "batch", "serve"), default="scene")
+    ap.add_argument("--jobs", type=int, default=16, help="serve: jobs per trace")
+    ap.add_argument("--no-autotune", action="store_true", help="batch: use the default launch shapes")
     ap.add_argument("--side", type=int, default=0, help="grid side (default: the workload's)")
     ap.add_argument("--cpu-sample-reorders", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -124,6 +294,10 @@ def main() -> int:
     import paper_2312_13299_amd as plas
     import synthetic
 
+    if args.workload == "batch":
+        return run_batch_workload(args, torch, plas, synthetic)
+    if args.workload == "serve":
+        return run_serve_workload(args, torch, plas, synthetic)
     precision = args.workload == "precision"
     side = args.side or (1448 if precision else 1024)
     data_seed = synthetic.DATA_SEED_PRECISION if precision else synthetic.DATA_SEED_SCENE

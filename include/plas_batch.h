@@ -52,7 +52,7 @@ typedef struct {
 typedef struct {
     int32_t side_lo;
     int32_t side_hi;
-    int32_t blur_waves_per_block; /* 64-channel blur: lines (one per wave) per block, 1, 2 or 4; 0: 4 */
+    int32_t blur_waves_per_block; /* 64-channel blur: lines (one per wave) per block, 1, 2 or 4; 0: 2 */
     int32_t assign_blocks;        /* blocks per sort for the assignment; 0: the plas_sort default */
 } plas_tune_entry;
 

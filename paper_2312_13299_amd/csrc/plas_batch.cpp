@@ -21,7 +21,7 @@ using namespace plas_host;
 
 namespace {
 
-constexpr int kDefaultWavesPerBlock = 4;
+constexpr int kDefaultWavesPerBlock = 2;  // as plas_sort
 constexpr int kMaxSlots = 1 << 16;     // grid index field of a block map entry
 constexpr int kMaxLocalBlocks = 1 << 16;  // block index field
 
@@ -723,8 +723,8 @@ int32_t plas_autotune_batch(plas_handle h, const plas_batch_item* items, int32_t
     double best_ms = 1e300;
     e.blur_waves_per_block = kDefaultWavesPerBlock;
     e.assign_blocks = 0;
-    for (int wpb : {4, 2, 1}) {
-      if (!has64 && wpb != 4) continue;
+    for (int wpb : {2, 1, 4}) {
+      if (!has64 && wpb != kDefaultWavesPerBlock) continue;
       plas_tune_entry cand = e;
       cand.blur_waves_per_block = wpb;
       double ms = 0.0;

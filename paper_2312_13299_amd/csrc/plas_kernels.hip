@@ -31,9 +31,9 @@ constexpr int kRangeBlocks = 256;
 #ifndef PLAS_ASSIGN_MAX_BLOCKS
 #define PLAS_ASSIGN_MAX_BLOCKS 4096
 #endif
-#ifndef PLAS_BLUR_LINES_PER_WAVE
-#define PLAS_BLUR_LINES_PER_WAVE 1
-#endif
+// Lines (one per wave) per block of the 64-channel blur: two-wave blocks of
+// 48 KB LDS let three blocks share a CU.
+constexpr int kBlurWavesPerBlock = 2;
 constexpr int kMaxGridBlocks = 4096;
 
 inline int blocks_for(int64_t threads, int64_t cap = kMaxGridBlocks) {
@@ -988,8 +988,13 @@ __device__ __forceinline__ void assign_items(S* __restrict__ G, const S* __restr
   }
 }
 
+#ifndef PLAS_ASSIGN_WAVES_PER_EU
+#define PLAS_ASSIGN_WAVES_PER_EU 4
+#endif
+
 template <int DP, typename S>
-__global__ __launch_bounds__(kBlock) void k_assign(S* __restrict__ G, const S* __restrict__ T,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PLAS_ASSIGN_WAVES_PER_EU)))
+void k_assign(S* __restrict__ G, const S* __restrict__ T,
                                                    int32_t* __restrict__ P,
                                                    const int32_t* __restrict__ table,
                                                    DevState* __restrict__ st) {
@@ -1216,7 +1221,8 @@ __global__ __launch_bounds__(kBlock) void k_blur_batch(const BatchGrid* __restri
 }
 
 template <int DP, typename S>
-__global__ __launch_bounds__(kBlock) void k_assign_batch(const BatchGrid* __restrict__ grids,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PLAS_ASSIGN_WAVES_PER_EU)))
+void k_assign_batch(const BatchGrid* __restrict__ grids,
                                                          const uint32_t* __restrict__ map, int state_idx) {
   uint32_t local;
   const BatchGridView& g = batch_grid(grids, map, local);
@@ -1336,10 +1342,9 @@ hipError_t launch_gather(const void* X, const int32_t* P, void* G, int64_t n, in
 hipError_t launch_blur_pass(const void* in, void* out, int w, int dp, int storage, const DevState* st,
                             int radius, int vertical, const float* inv, hipStream_t stream) {
   if (dp == 64) {
-    const int lines_per_block = kWavesPerBlock * PLAS_BLUR_LINES_PER_WAVE;
-    const int blocks = (w + lines_per_block - 1) / lines_per_block;
+    const int blocks = (w + kBlurWavesPerBlock - 1) / kBlurWavesPerBlock;
     PLAS_DISPATCH_STORAGE(storage, {
-      k_blur_staged64<SV, kWavesPerBlock><<<blocks, kBlock, 0, stream>>>(
+      k_blur_staged64<SV, kBlurWavesPerBlock><<<blocks, kBlurWavesPerBlock * 64, 0, stream>>>(
           static_cast<const SV*>(in), static_cast<SV*>(out), w, st, radius, vertical, inv);
     });
     return hipGetLastError();
