@@ -155,6 +155,17 @@ int32_t plas_grid_energy(plas_handle h, const void* features, const int32_t* per
                          int32_t radius, uint64_t* energy_fixed, int32_t* scale_shift,
                          double* energy_mean);
 
+/*
+ * VAD, the sort-quality measure of App. C: the population variance of the
+ * absolute differences |a - b| between the values of right and down
+ * neighbouring cells (no wrap-around) of the arranged grid
+ * features[perm] (perm: device int32[n] in gather form, or NULL for the
+ * identity), over every channel, computed in float64 in two passes (mean,
+ * then mean squared deviation). Lower is smoother. vad: host output.
+ */
+int32_t plas_vad(plas_handle h, const void* features, const int32_t* perm, int64_t n, int32_t d,
+                 int32_t side, int32_t layout, int32_t dtype, double* vad);
+
 /* A static string naming a status code. */
 const char* plas_status_string(int32_t status);
 

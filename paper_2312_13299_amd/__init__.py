@@ -41,7 +41,7 @@ MAX_CHANNELS = 64
 EXPORTS = (
     "plas_get_abi_version", "plas_sort_params_init", "plas_create", "plas_destroy",
     "plas_set_stream", "plas_sort", "plas_grid_energy", "plas_status_string", "plas_last_error",
-    "plas_stage_blur", "plas_stage_group_table", "plas_stage_assign", "plas_stage_energy",
+    "plas_vad", "plas_stage_blur", "plas_stage_group_table", "plas_stage_assign", "plas_stage_energy",
     "plas_stage_bijection", "plas_philox4x64_10", "plas_draw", "plas_schedule",
     "plas_scale_shift_from_ranges",
     "plas_batch_config_init", "plas_sort_batch", "plas_autotune_batch",
@@ -183,6 +183,7 @@ def library() -> ctypes.CDLL:
                             ctypes.POINTER(SortStats)]),
         "plas_grid_energy": (i32, [vp, vp, vp, i64, i32, i32, i32, i32, i32, i32, u64p, i32p,
                                    ctypes.POINTER(ctypes.c_double)]),
+        "plas_vad": (i32, [vp, vp, vp, i64, i32, i32, i32, i32, ctypes.POINTER(ctypes.c_double)]),
         "plas_status_string": (ctypes.c_char_p, [i32]),
         "plas_last_error": (ctypes.c_char_p, [vp]),
         "plas_stage_blur": (i32, [vp, vp, vp, i32, i32, i32, i32]),
@@ -460,6 +461,29 @@ class Context:
                                         ctypes.byref(s), ctypes.byref(mean))
         self._check(st, "plas_grid_energy")
         return int(E.value), s.value, mean.value
+
+    def vad(self, features, perm=None, side: int | None = None, layout: str = "cn") -> float:
+        """VAD (App. C) of features[perm] on the side x side grid."""
+        import torch
+        dtype = _feature_dtype(features)
+        if layout == "cn":
+            d, n = features.shape
+            lay = LAYOUT_CN
+        else:
+            n, d = features.shape
+            lay = LAYOUT_NC
+        if side is None:
+            side = int(round(n ** 0.5))
+        p = None
+        if perm is not None:
+            _check_tensor(perm, torch.int32)
+            p = ctypes.c_void_p(perm.data_ptr())
+        v = ctypes.c_double()
+        self._bind_stream()
+        st = library().plas_vad(self._h, ctypes.c_void_p(features.data_ptr()), p, n, d, side, lay, dtype,
+                                ctypes.byref(v))
+        self._check(st, "plas_vad")
+        return v.value
 
     # ---- stages (working layout [n][dp] float32)
 

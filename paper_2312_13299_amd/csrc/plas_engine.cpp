@@ -103,7 +103,7 @@ int32_t plas_destroy(plas_handle h) {
   release_batch_state(h);
   DeviceBuffer* bufs[] = {&h->grid_g, &h->grid_h, &h->grid_t, &h->perm, &h->table, &h->inv,
                           &h->range_part, &h->range_out, &h->levels, &h->trace, &h->state,
-                          &h->stage_state, &h->scratch};
+                          &h->stage_state, &h->scratch, &h->vad};
   for (DeviceBuffer* b : bufs) release(*b);
   if (h->status_host) (void)hipHostFree(h->status_host);
   if (h->range_host) (void)hipHostFree(h->range_host);
@@ -312,6 +312,32 @@ int32_t plas_grid_energy(plas_handle h, const void* features, const int32_t* per
   if (energy_fixed) *energy_fixed = E;
   if (scale_shift_out) *scale_shift_out = s;
   if (energy_mean) *energy_mean = std::ldexp(static_cast<double>(E), -s) / static_cast<double>(n);
+  return PLAS_OK;
+}
+
+int32_t plas_vad(plas_handle h, const void* features, const int32_t* perm, int64_t n, int32_t d, int32_t side,
+                 int32_t layout, int32_t dtype, double* vad) {
+  int32_t st = check_features(h, features, n, d, side, layout, dtype);
+  if (st != PLAS_OK) return st;
+  h->error.clear();
+  if (vad == nullptr) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "vad is NULL");
+  DeviceScope scope(h->device);
+  if (!scope.ok()) return fail(h, PLAS_ERR_HIP, "hipSetDevice failed");
+  if (perm != nullptr) {
+    PLAS_HIP(h, reserve(h->grid_h, static_cast<size_t>(n) * sizeof(int32_t)));
+    st = check_permutation(h, perm, n, as<int32_t>(h->grid_h));
+    if (st != PLAS_OK) return st;
+  }
+  const size_t parts = plas::vad_partial_doubles();
+  PLAS_HIP(h, reserve(h->vad, (parts + 2) * sizeof(double)));
+  double* part = as<double>(h->vad);
+  double* out = part + parts;
+  PLAS_HIP(h, plas::launch_vad(features, dtype == PLAS_DTYPE_BF16, perm, n, d, side, layout, part, out, h->stream));
+  PLAS_HIP(h, hipMemcpyAsync(h->u64_host, out, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  PLAS_HIP(h, hipStreamSynchronize(h->stream));
+  double v[2];
+  std::memcpy(v, h->u64_host, sizeof(v));
+  *vad = v[1];
   return PLAS_OK;
 }
 

@@ -53,6 +53,7 @@ struct plas_context {
   plas_host::DeviceBuffer state;                   // two DevStates of a sort (read one, write the other)
   plas_host::DeviceBuffer stage_state;             // DevState of a stage call
   plas_host::DeviceBuffer scratch;                 // u64 accumulators and flags
+  plas_host::DeviceBuffer vad;                     // VAD partial sums and results
   // Pinned host memory for small read-backs.
   HostStatus* status_host = nullptr;
   float* range_host = nullptr;

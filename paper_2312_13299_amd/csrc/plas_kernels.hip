@@ -265,57 +265,77 @@ struct BlurLine {
   __device__ __forceinline__ float load(int t) const {
     return Storage<S>::widen(src[static_cast<int64_t>(t) * step]);
   }
-  __device__ __forceinline__ void store(int x, float s) const {
+  // float32(1/count) of output position x (window clipped to the line).
+  __device__ __forceinline__ float mult(int x) const {
     const int hi = x + r < w - 1 ? x + r : w - 1;
     const int lo = x - r > 0 ? x - r : 0;
-    dst[static_cast<int64_t>(x) * step] = Storage<S>::narrow(s * inv[hi - lo + 1]);
+    return inv[hi - lo + 1];
+  }
+  __device__ __forceinline__ void store(int x, float s, float m) const {
+    dst[static_cast<int64_t>(x) * step] = Storage<S>::narrow(s * m);
   }
 };
 
+// kBlurUnroll positions' entering values, leaving values and multipliers.
+struct BlurBlock {
+  float enter[kBlurUnroll];
+  float leave[kBlurUnroll];
+  float mult[kBlurUnroll];
+};
+
 template <bool ENTER, bool LEAVE, typename L_t>
-__device__ __forceinline__ void blur_fetch(const L_t& L, int x0, float* enter, float* leave) {
+__device__ __forceinline__ void blur_fetch(const L_t& L, int x0, BlurBlock& B) {
 #pragma unroll
   for (int i = 0; i < kBlurUnroll; ++i) {
-    if (ENTER) enter[i] = L.load(x0 + i + L.r);
-    if (LEAVE) leave[i] = L.load(x0 + i - L.r - 1);
+    if (ENTER) B.enter[i] = L.load(x0 + i + L.r);
+    if (LEAVE) B.leave[i] = L.load(x0 + i - L.r - 1);
+    B.mult[i] = L.mult(x0 + i);
   }
 }
 
 template <bool ENTER, bool LEAVE, typename L_t>
-__device__ __forceinline__ void blur_apply(const L_t& L, int x0, const float* enter, const float* leave,
-                                           float& s) {
+__device__ __forceinline__ void blur_apply(const L_t& L, int x0, const BlurBlock& B, float& s) {
 #pragma unroll
   for (int i = 0; i < kBlurUnroll; ++i) {
-    if (ENTER) s = s + enter[i];
-    if (LEAVE) s = s - leave[i];
-    L.store(x0 + i, s);
+    if (ENTER) s = s + B.enter[i];
+    if (LEAVE) s = s - B.leave[i];
+    L.store(x0 + i, s, B.mult[i]);
   }
+}
+
+// Wait until every vector memory operation of this wave has completed
+// (s_waitcnt vmcnt(0); expcnt and lgkmcnt left at their maxima).
+__device__ __forceinline__ void wait_vmem() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 // Positions [xb, xe) where entering/leaving values exist as ENTER/LEAVE say.
+// Loads and stores share one memory counter, so with the previous block's
+// stores in flight the compiler can only wait for all outstanding memory
+// operations before a block's values are used; left to itself it would do
+// so after the next block's loads were issued and wait for those too. The
+// explicit wait comes first, the next block's fetch is issued after it and
+// flies while the current block is summed and stored.
 template <bool ENTER, bool LEAVE, typename L_t>
 __device__ __forceinline__ void blur_range(const L_t& L, int xb, int xe, float& s) {
   const int full = (xe - xb) / kBlurUnroll;
   int x = xb;
   if (full > 0) {
-    float ea[kBlurUnroll], la[kBlurUnroll], eb[kBlurUnroll], lb[kBlurUnroll];
-    blur_fetch<ENTER, LEAVE>(L, x, ea, la);
-    int c = 0;
-    for (;;) {
-      if (c + 1 < full) blur_fetch<ENTER, LEAVE>(L, x + kBlurUnroll, eb, lb);
-      blur_apply<ENTER, LEAVE>(L, x, ea, la, s);
+    BlurBlock next, cur;
+    blur_fetch<ENTER, LEAVE>(L, x, next);
+    for (int c = 0; c < full; ++c) {
+      wait_vmem();
+      cur = next;
+      if (c + 1 < full) blur_fetch<ENTER, LEAVE>(L, x + kBlurUnroll, next);
+      blur_apply<ENTER, LEAVE>(L, x, cur, s);
       x += kBlurUnroll;
-      if (++c == full) break;
-      if (c + 1 < full) blur_fetch<ENTER, LEAVE>(L, x + kBlurUnroll, ea, la);
-      blur_apply<ENTER, LEAVE>(L, x, eb, lb, s);
-      x += kBlurUnroll;
-      if (++c == full) break;
     }
   }
   for (; x < xe; ++x) {
     if (ENTER) s = s + L.load(x + L.r);
     if (LEAVE) s = s - L.load(x - L.r - 1);
-    L.store(x, s);
+    L.store(x, s, L.mult(x));
   }
 }
 
@@ -352,7 +372,7 @@ __device__ __forceinline__ void blur_reg_lines(const S* __restrict__ in, S* __re
     for (int i = 0; i < kBlurUnroll; ++i) s = s + v[i];
   }
   for (; t <= first_hi; ++t) s = s + L.load(t);
-  L.store(0, s);
+  L.store(0, s, L.mult(0));
   // Position x has an entering value iff x + r <= w - 1 and a leaving value
   // iff x - r - 1 >= 0. Both bounds split [1, w) into at most three ranges.
   const int enter_end = w - r < 1 ? 1 : (w - r > w ? w : w - r);  // x < enter_end: entering
@@ -1030,6 +1050,67 @@ __global__ __launch_bounds__(kBlock) void k_energy(const S* __restrict__ G, cons
   if (lane == 0) atomicAdd(out, acc);
 }
 
+// -------------------------------------------------------------------- VAD
+
+// The quality measure of App. C: the population variance of |a - b| over the
+// right and down neighbour pairs of the arranged grid, every channel, in
+// float64, in two passes (the mean, then the mean squared deviation). Each
+// block writes its partial sum; one block adds the partials in a fixed
+// order, so the result does not depend on scheduling.
+template <typename SI>
+__device__ __forceinline__ double feature(const SI* __restrict__ F, int64_t n, int d, int layout, int64_t i,
+                                          int c) {
+  const SI v = layout == 0 ? F[static_cast<int64_t>(c) * n + i] : F[i * d + c];
+  return static_cast<double>(Storage<SI>::widen(v));
+}
+
+template <typename SI>
+__global__ __launch_bounds__(kBlock) void k_vad_partial(const SI* __restrict__ F, const int32_t* __restrict__ perm,
+                                                        int64_t n, int d, int w, int layout, int pass,
+                                                        const double* __restrict__ mean_in,
+                                                        double* __restrict__ part) {
+  __shared__ double s_acc[kBlock];
+  const double mean = pass == 0 ? 0.0 : mean_in[0];
+  double acc = 0.0;
+  for (int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; p < n;
+       p += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int y = static_cast<int>(p / w), x = static_cast<int>(p - static_cast<int64_t>(y) * w);
+    const int64_t a = perm != nullptr ? perm[p] : p;
+    for (int dir = 0; dir < 2; ++dir) {
+      const int yy = y + (dir == 1), xx = x + (dir == 0);
+      if (yy >= w || xx >= w) continue;
+      const int64_t q = static_cast<int64_t>(yy) * w + xx;
+      const int64_t b = perm != nullptr ? perm[q] : q;
+      for (int c = 0; c < d; ++c) {
+        const double v = fabs(feature(F, n, d, layout, a, c) - feature(F, n, d, layout, b, c));
+        acc += pass == 0 ? v : (v - mean) * (v - mean);
+      }
+    }
+  }
+  s_acc[threadIdx.x] = acc;
+  __syncthreads();
+  for (int stride = kBlock / 2; stride > 0; stride >>= 1) {
+    if (threadIdx.x < stride) s_acc[threadIdx.x] += s_acc[threadIdx.x + stride];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s_acc[0];
+}
+
+// out[0] = sum of part[0 .. nparts) / count (one block of kBlock threads).
+__global__ __launch_bounds__(kBlock) void k_vad_finish(const double* __restrict__ part, int nparts, double count,
+                                                       double* __restrict__ out) {
+  __shared__ double s_acc[kBlock];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) acc += part[i];
+  s_acc[threadIdx.x] = acc;
+  __syncthreads();
+  for (int stride = kBlock / 2; stride > 0; stride >>= 1) {
+    if (threadIdx.x < stride) s_acc[threadIdx.x] += s_acc[threadIdx.x + stride];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s_acc[0] / count;
+}
+
 // -------------------------------------------------------------- controller
 
 // The control step after each reorder (Sec. 3.1), applied to a state copy:
@@ -1393,6 +1474,27 @@ hipError_t launch_energy(const void* G, const void* T, int64_t n, int dp, int st
     PLAS_DISPATCH_DP(dp, (k_energy<DPV, SV><<<blocks, kBlock, 0, stream>>>(
                              static_cast<const SV*>(G), static_cast<const SV*>(T), n, scale, energy_out)));
   });
+  return hipGetLastError();
+}
+
+// ---- VAD
+
+size_t vad_partial_doubles() { return kMaxGridBlocks; }
+
+hipError_t launch_vad(const void* features, int input_bf16, const int32_t* perm, int64_t n, int d, int w,
+                      int layout, double* part, double* out, hipStream_t stream) {
+  const int blocks = blocks_for(n);
+  const double count = static_cast<double>(d) * 2.0 * w * (w - 1);
+  // out[0]: mean |a - b|; out[1]: the variance.
+  for (int pass = 0; pass < 2; ++pass) {
+    if (input_bf16)
+      k_vad_partial<uint16_t><<<blocks, kBlock, 0, stream>>>(static_cast<const uint16_t*>(features), perm, n, d, w,
+                                                             layout, pass, out, part);
+    else
+      k_vad_partial<float><<<blocks, kBlock, 0, stream>>>(static_cast<const float*>(features), perm, n, d, w,
+                                                          layout, pass, out, part);
+    k_vad_finish<<<1, kBlock, 0, stream>>>(part, blocks, count, out + pass);
+  }
   return hipGetLastError();
 }
 

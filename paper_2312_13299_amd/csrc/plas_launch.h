@@ -59,6 +59,13 @@ hipError_t launch_assign(void* G, const void* T, int32_t* P, const int32_t* tabl
 // table of the next reorder. in and out are two different state buffers.
 hipError_t launch_step(const DevState* in, DevState* out, const LevelInfo* levels, plas_level_out* trace,
                        int32_t* table, int64_t max_cells, hipStream_t stream);
+// VAD (App. C) of features[perm] on a w x w grid: out[0] receives the mean
+// |a - b| over neighbour pairs and channels, out[1] the variance. part:
+// device scratch of vad_partial_doubles() doubles; out: device double[2].
+size_t vad_partial_doubles();
+hipError_t launch_vad(const void* features, int input_bf16, const int32_t* perm, int64_t n, int d, int w,
+                      int layout, double* part, double* out, hipStream_t stream);
+
 // ---- batches of sorts (BatchGrid in plas_device.h). A launch's block map
 // (device uint32[blocks]) holds (grid index << 16) | block index within the
 // grid's blocks; a grid's entries run from 0 to its block count - 1.

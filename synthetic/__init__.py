@@ -36,6 +36,7 @@ DATA_SEED_SCENE = 2       # 1024 x 1024 grid
 DATA_SEED_PRECISION = 3   # 1448 x 1448 grid
 SORT_SEED = 0x5EED
 DATA_SEED_BATCH = 4       # the 64-grid batch: sides and per-grid data seeds
+DATA_SEED_RGB = 5         # the random 512 x 512 x 3 grid of the runtime experiment
 BATCH_GRIDS = 64
 BATCH_SIDE_RANGE = (128, 724)
 

@@ -29,13 +29,18 @@ CASES = {
     "sort_1024_d59": dict(side=1024, data_seed=synthetic.DATA_SEED_SCENE, sort_seed=synthetic.SORT_SEED),
     # A mid-size case that the GPU test can also compare reorder by reorder.
     "sort_256_d59": dict(side=256, data_seed=11, sort_seed=synthetic.SORT_SEED),
+    # The runtime experiment of App. C: a random 512 x 512 grid of U(0, 255)
+    # RGB values; its VAD is stored as well.
+    "sort_512_rgb": dict(side=512, data_seed=synthetic.DATA_SEED_RGB, sort_seed=synthetic.SORT_SEED, rgb=True),
 }
 
 
 def run(name: str) -> dict:
     c = CASES[name]
     side = c["side"]
-    F = synthetic.gaussian_attributes(side * side, c["data_seed"])
+    rgb = c.get("rgb", False)
+    F = synthetic.random_rgb_grid(side, c["data_seed"]) if rgb else \
+        synthetic.gaussian_attributes(side * side, c["data_seed"])
     t0 = time.time()
     res = oracle.sort(F, side, c["sort_seed"], energy_cap=1 << 20)
     dt = time.time() - t0
@@ -47,7 +52,8 @@ def run(name: str) -> dict:
         "d": int(F.shape[0]),
         "data_seed": c["data_seed"],
         "sort_seed": c["sort_seed"],
-        "generator": "synthetic.gaussian_attributes (channel-major float32)",
+        "generator": ("synthetic.random_rgb_grid" if rgb else "synthetic.gaussian_attributes") +
+                     " (channel-major float32)",
         "reorders": int(res.reorders),
         "levels": int(res.levels),
         "scale_shift": int(res.scale_shift),
@@ -59,6 +65,8 @@ def run(name: str) -> dict:
                        energy=str(t["energy"]), moved=t["moved"]) for t in res.trace],
         "oracle_seconds": round(dt, 1),
         "oracle_threads": oracle.set_threads(0),
+        "vad_sorted": oracle.vad(F, res.perm, side),
+        "vad_start": oracle.vad(F, None, side),
     }
 
 
