@@ -251,7 +251,10 @@ __device__ __forceinline__ void wave_lds_sync() {
 // "a value enters" and "a value leaves" are fixed, which keeps the unrolled
 // loops free of per-position tests; the position x is the same for all lanes
 // of a wave, so every remaining branch is uniform.
-constexpr int kBlurUnroll = 12;
+#ifndef PLAS_BLUR_UNROLL
+#define PLAS_BLUR_UNROLL 12
+#endif
+constexpr int kBlurUnroll = PLAS_BLUR_UNROLL;
 
 template <typename S>
 struct BlurLine {
@@ -274,6 +277,8 @@ struct BlurLine {
   __device__ __forceinline__ void store(int x, float s, float m) const {
     dst[static_cast<int64_t>(x) * step] = Storage<S>::narrow(s * m);
   }
+  __device__ static __forceinline__ float widen(S v) { return Storage<S>::widen(v); }
+  __device__ static __forceinline__ S narrow(float v) { return Storage<S>::narrow(v); }
 };
 
 // kBlurUnroll positions' entering values, leaving values and multipliers.
@@ -283,23 +288,37 @@ struct BlurBlock {
   float mult[kBlurUnroll];
 };
 
+// Addresses advance by one step per position (a 64-bit add) instead of
+// being recomputed from the position (a 64-bit multiply each).
 template <bool ENTER, bool LEAVE, typename L_t>
 __device__ __forceinline__ void blur_fetch(const L_t& L, int x0, BlurBlock& B) {
+  const auto* pe = L.src;
+  const auto* pl = L.src;
+  if (ENTER) pe += static_cast<int64_t>(x0 + L.r) * L.step;
+  if (LEAVE) pl += static_cast<int64_t>(x0 - L.r - 1) * L.step;
 #pragma unroll
   for (int i = 0; i < kBlurUnroll; ++i) {
-    if (ENTER) B.enter[i] = L.load(x0 + i + L.r);
-    if (LEAVE) B.leave[i] = L.load(x0 + i - L.r - 1);
+    if (ENTER) {
+      B.enter[i] = L.widen(*pe);
+      pe += L.step;
+    }
+    if (LEAVE) {
+      B.leave[i] = L.widen(*pl);
+      pl += L.step;
+    }
     B.mult[i] = L.mult(x0 + i);
   }
 }
 
 template <bool ENTER, bool LEAVE, typename L_t>
 __device__ __forceinline__ void blur_apply(const L_t& L, int x0, const BlurBlock& B, float& s) {
+  auto* pd = L.dst + static_cast<int64_t>(x0) * L.step;
 #pragma unroll
   for (int i = 0; i < kBlurUnroll; ++i) {
     if (ENTER) s = s + B.enter[i];
     if (LEAVE) s = s - B.leave[i];
-    L.store(x0 + i, s, B.mult[i]);
+    *pd = L.narrow(s * B.mult[i]);
+    pd += L.step;
   }
 }
 
@@ -309,6 +328,7 @@ __device__ __forceinline__ void wait_vmem() {
   __builtin_amdgcn_s_waitcnt(0x0F70);
   __builtin_amdgcn_sched_barrier(0);
 }
+
 
 // Positions [xb, xe) where entering/leaving values exist as ENTER/LEAVE say.
 // Loads and stores share one memory counter, so with the previous block's
@@ -470,18 +490,33 @@ struct StagedLine {
   __device__ __forceinline__ void fetch(int c, StagedRegs<S>& R) const {
     const bool init = c < n_init;
     const int base = init ? c * kChunk : 1 + (c - n_init) * kChunk;
+    if (!init && base - r - 1 >= 0 && base + kChunk - 1 + r <= w - 1) {
+      // Every entering and leaving position of the chunk lies in the line:
+      // walk both streams with one pointer step per load.
+      const uint4* pe = reinterpret_cast<const uint4*>(src + static_cast<int64_t>(base + r + q) * step) + j;
+      const uint4* pl = reinterpret_cast<const uint4*>(src + static_cast<int64_t>(base - r - 1 + q) * step) + j;
+      const int64_t inc = static_cast<int64_t>(Shape::kPos) * step * static_cast<int64_t>(sizeof(S)) / 16;
 #pragma unroll
-    for (int i = 0; i < Shape::kVec; ++i) {
-      const int x = base + Shape::kPos * i + q;
-      const int a = init ? x : x + r;
-      const int b = init ? x : x - r - 1;
-      R.enter[i] = ld(clamp_pos(a));
-      R.leave[i] = ld(clamp_pos(b));
+      for (int i = 0; i < Shape::kVec; ++i) {
+        R.enter[i] = pe[i * inc];
+        R.leave[i] = pl[i * inc];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < Shape::kVec; ++i) {
+        const int x = base + Shape::kPos * i + q;
+        const int a = init ? x : x + r;
+        const int b = init ? x : x - r - 1;
+        R.enter[i] = ld(clamp_pos(a));
+        R.leave[i] = ld(clamp_pos(b));
+      }
     }
+    // Output chunks: lane p's multiplier is that of position base + p;
+    // starting chunks: that of position 0 (window 0 .. first_hi).
     const int x = clamp_pos(base + (lane & (kChunk - 1)));
     const int hi = x + r < w - 1 ? x + r : w - 1;
     const int lo = x - r > 0 ? x - r : 0;
-    R.mult = inv[hi - lo + 1];
+    R.mult = inv[init ? first_hi + 1 : hi - lo + 1];
   }
 
   __device__ __forceinline__ void stage(const StagedRegs<S>& R) const {
@@ -495,20 +530,26 @@ struct StagedLine {
   // Output positions x0 .. x0 + kStageSub - 1 (LDS rows p0 ..), all inside
   // the grid, all with (ENTER) or without an entering value and all with
   // (LEAVE) or without a leaving one: no per-position tests.
+  // With both an entering and a leaving value at every position the window
+  // holds 2r + 1 cells, and with neither it is the whole line: one
+  // multiplier serves all positions (the same table entry the per-position
+  // lookup would give). Otherwise each position takes its own from lane p.
   template <bool ENTER, bool LEAVE>
   __device__ __forceinline__ void run_uniform(int p0, int mult_bits, float& s) const {
+    constexpr bool kConstMult = ENTER == LEAVE;
     float e[kStageSub], l[kStageSub];
 #pragma unroll
     for (int p = 0; p < kStageSub; ++p) {
       if (ENTER) e[p] = Storage<S>::widen(lds->enter[p0 + p][lane]);
       if (LEAVE) l[p] = Storage<S>::widen(lds->leave[p0 + p][lane]);
     }
+    const float m_const = kConstMult ? __int_as_float(__builtin_amdgcn_readlane(mult_bits, p0)) : 0.0f;
 #pragma unroll
     for (int p = 0; p < kStageSub; ++p) {
       if (ENTER) s = s + e[p];
       if (LEAVE) s = s - l[p];
-      lds->out[p0 + p][lane] =
-          Storage<S>::narrow(s * __int_as_float(__builtin_amdgcn_readlane(mult_bits, p0 + p)));
+      const float m = kConstMult ? m_const : __int_as_float(__builtin_amdgcn_readlane(mult_bits, p0 + p));
+      lds->out[p0 + p][lane] = Storage<S>::narrow(s * m);
     }
   }
 
@@ -556,7 +597,8 @@ struct StagedLine {
           }
         }
       }
-      if (c == n_init - 1) dst[lane] = Storage<S>::narrow(s * inv[first_hi + 1]);
+      if (c == n_init - 1)
+        dst[lane] = Storage<S>::narrow(s * __int_as_float(__builtin_amdgcn_readfirstlane(mult_bits)));
       return;
     }
     const int x0c = 1 + (c - n_init) * kChunk;
