@@ -78,7 +78,9 @@ typedef struct {
     double prepare_ms;      /* ingest, ranges and start arrangements of all sorts */
     double loop_ms;         /* the reorder loop */
     double total_ms;        /* the whole call */
-    double step_ms;         /* with config->profile: summed device times per launch kind */
+    double step_ms;         /* with config->profile: summed device times per launch kind; the
+                               controller step runs inside the row blur, so step_ms stays ~0
+                               and blur_ms includes it */
     double blur_ms;
     double assign_ms;
 } plas_batch_stats;

@@ -27,7 +27,7 @@ constexpr int kMaxLocalBlocks = 1 << 16;  // block index field
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
-enum LaunchKind { kStep = 0, kBlur = 1, kAssign = 2 };
+enum LaunchKind { kBlur = 1, kAssign = 2 };
 
 // Byte offsets of one sort's buffers in its allocation.
 struct SortLayout {
@@ -257,8 +257,7 @@ class BatchRun {
     g.trace = reinterpret_cast<plas_level_out*>(base + o_trace);
     g.states = reinterpret_cast<DevState*>(base + o_states);
     g.w = s.w;
-    g.step_blocks = plas::batch_step_blocks(s.max_cells);
-    g.blur_blocks = plas::batch_blur_blocks(s.w, s.dp, s.wpb);
+    g.blur_blocks = plas::batch_blur_blocks(s.w, s.dp, s.wpb, s.max_cells);
     g.assign_blocks = plas::batch_assign_blocks(s.max_items, s.dp, s.assign_cap);
 
     // Features -> X in T, the start arrangement, G = X[P] (as plas_sort).
@@ -455,7 +454,7 @@ class BatchRun {
       std::vector<uint32_t> map;
       for (int slot : members) {
         const plas::BatchGrid& g = sorts_[slot].grid;
-        const int nb = kind == kStep ? g.step_blocks : kind == kBlur ? g.blur_blocks : g.assign_blocks;
+        const int nb = kind == kBlur ? g.blur_blocks : g.assign_blocks;
         for (int b = 0; b < nb; ++b) map.push_back((static_cast<uint32_t>(slot) << 16) | static_cast<uint32_t>(b));
       }
       if (map.empty()) return;
@@ -464,7 +463,6 @@ class BatchRun {
       launches_.push_back(L);
       maps.push_back(std::move(map));
     };
-    add_launch(kStep, 0, 0, 0, run_list_);
     // Blur launches per (dp, storage, lines per block); assignment per (dp, storage).
     for (int pass = 0; pass < 2; ++pass) {
       std::vector<std::array<int, 3>> keys;
@@ -513,8 +511,9 @@ class BatchRun {
     return PLAS_OK;
   }
 
-  // chunk_ reorders: step (reads states[cur], writes states[cur ^ 1]), blur
-  // rows, blur columns, assignment, each over all running sorts.
+  // chunk_ reorders: blur rows (after each sort's controller step from
+  // states[cur] to states[cur ^ 1]), blur columns, assignment, each over all
+  // running sorts.
   int32_t enqueue_reorders(bool timed) {
     hipStream_t stream = b_->stream;
     const char* plan = static_cast<const char*>(b_->plan.ptr);
@@ -522,9 +521,6 @@ class BatchRun {
     auto map_of = [&](const Launch& L) { return reinterpret_cast<const uint32_t*>(plan + L.map_off); };
     for (int i = 0; i < chunk_; ++i) {
       if (timed) PLAS_HIP(h_, hipEventRecord(b_->events[4 * i + 0], stream));
-      const int src = cur_;
-      for (const Launch& L : launches_)
-        if (L.kind == kStep) PLAS_HIP(h_, plas::launch_step_batch(grids, map_of(L), L.blocks, src, stream));
       cur_ ^= 1;
       if (timed) PLAS_HIP(h_, hipEventRecord(b_->events[4 * i + 1], stream));
       for (int vertical = 0; vertical < 2; ++vertical)

@@ -71,9 +71,10 @@ struct HostStatus {
 
 struct plas_level_out;
 
-// One sort of a batch: its buffers, its two states (each reorder's step
-// reads one and writes the other), and how many blocks of each launch kind
-// it takes. Grids G, H, T are [w*w][dp] in the batch's storage.
+// One sort of a batch: its buffers, its two states (each reorder's
+// controller step reads one and writes the other), and how many blocks of
+// each launch kind it takes. Grids G, H, T are [w*w][dp] in the batch's
+// storage.
 struct BatchGrid {
   void* G;
   void* H;
@@ -85,9 +86,9 @@ struct BatchGrid {
   plas_level_out* trace;
   DevState* states;
   int32_t w;
-  int32_t step_blocks;
   int32_t blur_blocks;
   int32_t assign_blocks;
+  int32_t pad;
 };
 
 }  // namespace plas

@@ -204,11 +204,14 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
   int64_t slots = 0;  // reorder slots queued so far; slot i runs reorder i unless the sort has ended
   for (;;) {
     for (int i = 0; i < chunk; ++i) {
+      // The row pass first steps the controller from states[cur] to
+      // states[cur ^ 1] (and fills the grouping table); the rest of the
+      // reorder uses states[cur ^ 1].
       DevState* Sd = &states[cur ^ 1];
-      PLAS_HIP(h, plas::launch_step(&states[cur], Sd, Ld, Td, table, max_cells, h->stream));
+      const plas::StepArgs step{&states[cur], Sd, Ld, Td, table, max_cells};
       cur ^= 1;
       if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 0], h->stream));
-      PLAS_HIP(h, plas::launch_blur_pass(G, H, w, dp, storage, Sd, 0, 0, as<float>(h->inv), h->stream));
+      PLAS_HIP(h, plas::launch_blur_pass(G, H, w, dp, storage, nullptr, 0, 0, as<float>(h->inv), h->stream, &step));
       PLAS_HIP(h, plas::launch_blur_pass(H, T, w, dp, storage, Sd, 0, 1, as<float>(h->inv), h->stream));
       if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 1], h->stream));
       if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 2], h->stream));

@@ -17,6 +17,7 @@
 // equal, bit for bit, to a CPU that evaluates the same expressions.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
 
 #include "plas_launch.h"
@@ -228,6 +229,30 @@ __global__ __launch_bounds__(kBlock) void k_gather(const S* __restrict__ X, cons
 
 // ------------------------------------------------------------------- blur
 
+// The controller step of the previous reorder and the grouping table of the
+// next one, run by every block of a row pass before it blurs (defined with
+// the controller below). NT: threads per block.
+template <int NT>
+__device__ void step_body(const DevState* __restrict__ in, DevState* __restrict__ out,
+                          const LevelInfo* __restrict__ levels, plas_level_out* __restrict__ trace,
+                          int32_t* __restrict__ table, int64_t bid, int64_t nblocks, DevState& s_st);
+
+// The radius of a pass: after the step (step.in set), from the new state in
+// LDS; else from st, or the fixed radius when st is NULL. Returns false when
+// the sort has ended.
+template <int NT>
+__device__ __forceinline__ bool pass_radius(const StepArgs& step, const DevState* __restrict__ st, int radius,
+                                            int64_t bid, int64_t nblocks, DevState& s_st, int& r) {
+  if (step.in != nullptr) {
+    step_body<NT>(step.in, step.out, step.levels, step.trace, step.table, bid, nblocks, s_st);
+    r = s_st.r;
+    return !s_st.done;
+  }
+  if (st != nullptr && st->done) return false;
+  r = st != nullptr ? st->r : radius;
+  return true;
+}
+
 // Orders this wave's LDS writes before its later LDS reads (lanes of one
 // wave exchange data through LDS without a block barrier).
 __device__ __forceinline__ void wave_lds_sync() {
@@ -417,9 +442,10 @@ inline int64_t blur_reg_waves(int w) {
 template <int DP, typename S>
 __global__ __launch_bounds__(kBlock) void k_blur(const S* __restrict__ in, S* __restrict__ out,
                                                  int w, const DevState* __restrict__ st, int radius,
-                                                 int vertical, const float* __restrict__ inv) {
-  if (st != nullptr && st->done) return;
-  const int r = st != nullptr ? st->r : radius;
+                                                 int vertical, const float* __restrict__ inv, StepArgs step) {
+  __shared__ DevState s_st;
+  int r;
+  if (!pass_radius<kBlock>(step, st, radius, blockIdx.x, gridDim.x, s_st, r)) return;
   const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 6;
   blur_reg_lines<DP, S>(in, out, w, r, vertical, inv, wave, threadIdx.x & 63);
 }
@@ -684,10 +710,12 @@ __device__ __forceinline__ void blur_staged_lines(const S* __restrict__ in, S* _
 template <typename S, int WPB>
 __global__ __launch_bounds__(WPB * 64) void k_blur_staged64(const S* __restrict__ in, S* __restrict__ out, int w,
                                                             const DevState* __restrict__ st, int radius,
-                                                            int vertical, const float* __restrict__ inv) {
+                                                            int vertical, const float* __restrict__ inv,
+                                                            StepArgs step) {
   __shared__ StagedLds<S> s_stage[WPB];
-  if (st != nullptr && st->done) return;
-  const int r = st != nullptr ? st->r : radius;
+  __shared__ DevState s_st;
+  int r;
+  if (!pass_radius<WPB * 64>(step, st, radius, blockIdx.x, gridDim.x, s_st, r)) return;
   blur_staged_lines<S, WPB>(in, out, w, r, vertical, inv, blockIdx.x, gridDim.x, s_stage);
 }
 
@@ -695,12 +723,13 @@ __global__ __launch_bounds__(WPB * 64) void k_blur_staged64(const S* __restrict_
 
 // table[t] = pi(t) packed as (ly << 16) | lx, pi the grouping bijection of
 // a reorder over the beta^2 block-local cells, filled by all blocks.
+template <int NT = kBlock>
 __device__ __forceinline__ void fill_group_table(int32_t* __restrict__ table, int beta, const uint64_t keys[4],
                                                  int64_t bid, int64_t nblocks) {
   const uint64_t cells = static_cast<uint64_t>(beta) * beta;
   const Bijection f(cells, keys);
-  const uint64_t stride = static_cast<uint64_t>(nblocks) * kBlock;
-  for (uint64_t t = static_cast<uint64_t>(bid) * kBlock + threadIdx.x; t < cells; t += stride) {
+  const uint64_t stride = static_cast<uint64_t>(nblocks) * NT;
+  for (uint64_t t = static_cast<uint64_t>(bid) * NT + threadIdx.x; t < cells; t += stride) {
     const uint32_t v = static_cast<uint32_t>(f(t));
     const uint32_t ly = v / static_cast<uint32_t>(beta);
     const uint32_t lx = v - ly * static_cast<uint32_t>(beta);
@@ -1222,19 +1251,20 @@ __device__ void control_step(DevState& st, const LevelInfo* __restrict__ levels,
   }
 }
 
-// One launch between reorders: the control step of the reorder that just
-// ran and the grouping table of the next one. The state is double-buffered:
-// every block reads `in` (nothing writes it during this launch) and applies
-// the same control step to its own LDS copy, so all blocks agree on the next
-// beta and keys; block 0 alone writes `out` and the trace.
-__device__ __forceinline__ void step_body(const DevState* __restrict__ in, DevState* __restrict__ out,
-                                          const LevelInfo* __restrict__ levels, plas_level_out* __restrict__ trace,
-                                          int32_t* __restrict__ table, int64_t bid, int64_t nblocks,
-                                          DevState& s_st) {
+// Between reorders: the control step of the reorder that just ran and the
+// grouping table of the next one, run at the start of the next reorder's
+// row pass. The state is double-buffered: every block reads `in` (nothing
+// writes it during this launch) and applies the same control step to its
+// own LDS copy, so all blocks agree on the next radius, beta and keys; block
+// 0 alone writes `out` and the trace; the blocks fill the table together.
+template <int NT>
+__device__ void step_body(const DevState* __restrict__ in, DevState* __restrict__ out,
+                          const LevelInfo* __restrict__ levels, plas_level_out* __restrict__ trace,
+                          int32_t* __restrict__ table, int64_t bid, int64_t nblocks, DevState& s_st) {
   static_assert(sizeof(DevState) % 4 == 0, "state is copied as 32-bit words");
   constexpr int kWords = sizeof(DevState) / 4;
   uint32_t* words = reinterpret_cast<uint32_t*>(&s_st);
-  for (int i = threadIdx.x; i < kWords; i += kBlock) words[i] = reinterpret_cast<const uint32_t*>(in)[i];
+  for (int i = threadIdx.x; i < kWords; i += NT) words[i] = reinterpret_cast<const uint32_t*>(in)[i];
   __syncthreads();
   if (threadIdx.x == 0) {
     if (!s_st.done && s_st.pending) control_step(s_st, levels, bid == 0 ? trace : nullptr);
@@ -1246,17 +1276,9 @@ __device__ __forceinline__ void step_body(const DevState* __restrict__ in, DevSt
   }
   __syncthreads();
   if (bid == 0)
-    for (int i = threadIdx.x; i < kWords; i += kBlock) reinterpret_cast<uint32_t*>(out)[i] = words[i];
+    for (int i = threadIdx.x; i < kWords; i += NT) reinterpret_cast<uint32_t*>(out)[i] = words[i];
   if (s_st.done) return;
-  fill_group_table(table, s_st.beta, s_st.keys, bid, nblocks);
-}
-
-__global__ __launch_bounds__(kBlock) void k_step(const DevState* __restrict__ in, DevState* __restrict__ out,
-                                                 const LevelInfo* __restrict__ levels,
-                                                 plas_level_out* __restrict__ trace,
-                                                 int32_t* __restrict__ table) {
-  __shared__ DevState s_st;
-  step_body(in, out, levels, trace, table, blockIdx.x, gridDim.x, s_st);
+  fill_group_table<NT>(table, s_st.beta, s_st.keys, bid, nblocks);
 }
 
 // ------------------------------------------------------------------ batch
@@ -1283,9 +1305,9 @@ struct BatchGridView {
   plas_level_out PLAS_GLOBAL* trace;
   DevState PLAS_GLOBAL* states;
   int32_t w;
-  int32_t step_blocks;
   int32_t blur_blocks;
   int32_t assign_blocks;
+  int32_t pad;
 };
 static_assert(sizeof(BatchGridView) == sizeof(BatchGrid), "descriptor view layout");
 static_assert(offsetof(BatchGridView, w) == offsetof(BatchGrid, w), "descriptor view layout");
@@ -1304,14 +1326,18 @@ __device__ __forceinline__ T* global_ptr(U PLAS_GLOBAL* p) {
   return (T*)((T PLAS_GLOBAL*)p);
 }
 
-__global__ __launch_bounds__(kBlock) void k_step_batch(const BatchGrid* __restrict__ grids,
-                                                       const uint32_t* __restrict__ map, int src) {
-  __shared__ DevState s_st;
-  uint32_t local;
-  const BatchGridView& g = batch_grid(grids, map, local);
+// The row pass of a reorder first steps the sort's controller from state
+// state_idx ^ 1 to state_idx (the one the reorder then uses).
+__device__ __forceinline__ StepArgs batch_step(const BatchGridView& g, int state_idx, int vertical) {
+  StepArgs a{};  // table_cells is a host-side launch-size hint, unused here
+  if (vertical) return a;
   DevState* states = global_ptr<DevState>(g.states);
-  step_body(states + src, states + (src ^ 1), global_ptr<const LevelInfo>(g.levels),
-            global_ptr<plas_level_out>(g.trace), global_ptr<int32_t>(g.table), local, g.step_blocks, s_st);
+  a.in = states + (state_idx ^ 1);
+  a.out = states + state_idx;
+  a.levels = global_ptr<const LevelInfo>(g.levels);
+  a.trace = global_ptr<plas_level_out>(g.trace);
+  a.table = global_ptr<int32_t>(g.table);
+  return a;
 }
 
 template <typename S, int WPB>
@@ -1319,28 +1345,33 @@ __global__ __launch_bounds__(WPB * 64) void k_blur_staged64_batch(const BatchGri
                                                                   const uint32_t* __restrict__ map,
                                                                   int state_idx, int vertical) {
   __shared__ StagedLds<S> s_stage[WPB];
+  __shared__ DevState s_st;
   uint32_t local;
   const BatchGridView& g = batch_grid(grids, map, local);
-  const DevState* st = global_ptr<const DevState>(g.states) + state_idx;
-  if (st->done) return;
+  int r;
+  if (!pass_radius<WPB * 64>(batch_step(g, state_idx, vertical), global_ptr<const DevState>(g.states) + state_idx,
+                             0, local, g.blur_blocks, s_st, r))
+    return;
   const S* in = global_ptr<const S>(vertical ? g.H : g.G);
   S* out = global_ptr<S>(vertical ? g.T : g.H);
-  blur_staged_lines<S, WPB>(in, out, g.w, st->r, vertical, global_ptr<const float>(g.inv), local, g.blur_blocks,
-                            s_stage);
+  blur_staged_lines<S, WPB>(in, out, g.w, r, vertical, global_ptr<const float>(g.inv), local, g.blur_blocks, s_stage);
 }
 
 template <int DP, typename S>
 __global__ __launch_bounds__(kBlock) void k_blur_batch(const BatchGrid* __restrict__ grids,
                                                        const uint32_t* __restrict__ map, int state_idx,
                                                        int vertical) {
+  __shared__ DevState s_st;
   uint32_t local;
   const BatchGridView& g = batch_grid(grids, map, local);
-  const DevState* st = global_ptr<const DevState>(g.states) + state_idx;
-  if (st->done) return;
+  int r;
+  if (!pass_radius<kBlock>(batch_step(g, state_idx, vertical), global_ptr<const DevState>(g.states) + state_idx, 0,
+                           local, g.blur_blocks, s_st, r))
+    return;
   const S* in = global_ptr<const S>(vertical ? g.H : g.G);
   S* out = global_ptr<S>(vertical ? g.T : g.H);
   const int64_t wave = (static_cast<int64_t>(local) * kBlock + threadIdx.x) >> 6;
-  blur_reg_lines<DP, S>(in, out, g.w, st->r, vertical, global_ptr<const float>(g.inv), wave, threadIdx.x & 63);
+  blur_reg_lines<DP, S>(in, out, g.w, r, vertical, global_ptr<const float>(g.inv), wave, threadIdx.x & 63);
 }
 
 template <int DP, typename S>
@@ -1463,21 +1494,29 @@ hipError_t launch_gather(const void* X, const int32_t* P, void* G, int64_t n, in
 }
 
 hipError_t launch_blur_pass(const void* in, void* out, int w, int dp, int storage, const DevState* st,
-                            int radius, int vertical, const float* inv, hipStream_t stream) {
+                            int radius, int vertical, const float* inv, hipStream_t stream, const StepArgs* step) {
+  const StepArgs sa = step != nullptr ? *step : StepArgs{};
+  // With the step, also enough blocks to fill the grouping table at about
+  // one entry per thread (blocks beyond the lines only do that).
+  auto with_table = [&](int blocks, int threads) {
+    if (sa.in == nullptr) return blocks;
+    const int64_t need = std::min<int64_t>(1024, (sa.table_cells + threads - 1) / threads);
+    return static_cast<int>(std::max<int64_t>(blocks, need));
+  };
   if (dp == 64) {
-    const int blocks = (w + kBlurWavesPerBlock - 1) / kBlurWavesPerBlock;
+    const int blocks = with_table((w + kBlurWavesPerBlock - 1) / kBlurWavesPerBlock, kBlurWavesPerBlock * 64);
     PLAS_DISPATCH_STORAGE(storage, {
       k_blur_staged64<SV, kBlurWavesPerBlock><<<blocks, kBlurWavesPerBlock * 64, 0, stream>>>(
-          static_cast<const SV*>(in), static_cast<SV*>(out), w, st, radius, vertical, inv);
+          static_cast<const SV*>(in), static_cast<SV*>(out), w, st, radius, vertical, inv, sa);
     });
     return hipGetLastError();
   }
   int64_t waves = 0;
   PLAS_DISPATCH_DP(dp, waves = blur_reg_waves<DPV>(w));
-  const int blocks = static_cast<int>((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+  const int blocks = with_table(static_cast<int>((waves + kWavesPerBlock - 1) / kWavesPerBlock), kBlock);
   PLAS_DISPATCH_STORAGE(storage, {
     PLAS_DISPATCH_DP(dp, (k_blur<DPV, SV><<<blocks, kBlock, 0, stream>>>(
-                             static_cast<const SV*>(in), static_cast<SV*>(out), w, st, radius, vertical, inv)));
+                             static_cast<const SV*>(in), static_cast<SV*>(out), w, st, radius, vertical, inv, sa)));
   });
   return hipGetLastError();
 }
@@ -1497,12 +1536,6 @@ hipError_t launch_assign(void* G, const void* T, int32_t* P, const int32_t* tabl
     PLAS_DISPATCH_DP(dp, (k_assign<DPV, SV><<<blocks, kBlock, 0, stream>>>(
                              static_cast<SV*>(G), static_cast<const SV*>(T), P, table, st)));
   });
-  return hipGetLastError();
-}
-
-hipError_t launch_step(const DevState* in, DevState* out, const LevelInfo* levels, plas_level_out* trace,
-                       int32_t* table, int64_t max_cells, hipStream_t stream) {
-  k_step<<<blocks_for(max_cells, 1024), kBlock, 0, stream>>>(in, out, levels, trace, table);
   return hipGetLastError();
 }
 
@@ -1542,18 +1575,24 @@ hipError_t launch_vad(const void* features, int input_bf16, const int32_t* perm,
 
 // ---- batch
 
-int batch_step_blocks(int64_t max_cells) { return blocks_for(max_cells, 1024); }
-
-int batch_blur_blocks(int w, int dp, int waves_per_block) {
-  if (dp == 64) return (w + waves_per_block - 1) / waves_per_block;
-  int64_t waves = 0;
-  switch (dp) {
-    case 4: waves = blur_reg_waves<4>(w); break;
-    case 8: waves = blur_reg_waves<8>(w); break;
-    case 16: waves = blur_reg_waves<16>(w); break;
-    default: waves = blur_reg_waves<32>(w); break;
+int batch_blur_blocks(int w, int dp, int waves_per_block, int64_t max_cells) {
+  int64_t blocks = 0, threads = 0;
+  if (dp == 64) {
+    blocks = (w + waves_per_block - 1) / waves_per_block;
+    threads = 64 * waves_per_block;
+  } else {
+    int64_t waves = 0;
+    switch (dp) {
+      case 4: waves = blur_reg_waves<4>(w); break;
+      case 8: waves = blur_reg_waves<8>(w); break;
+      case 16: waves = blur_reg_waves<16>(w); break;
+      default: waves = blur_reg_waves<32>(w); break;
+    }
+    blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    threads = kBlock;
   }
-  return static_cast<int>((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+  const int64_t need = std::min<int64_t>(1024, (max_cells + threads - 1) / threads);
+  return static_cast<int>(std::max(blocks, need));
 }
 
 int batch_assign_blocks(int64_t max_items, int dp, int cap) {
@@ -1563,12 +1602,6 @@ int batch_assign_blocks(int64_t max_items, int dp, int cap) {
 }
 
 int default_assign_blocks_cap() { return PLAS_ASSIGN_MAX_BLOCKS; }
-
-hipError_t launch_step_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int src,
-                             hipStream_t stream) {
-  k_step_batch<<<blocks, kBlock, 0, stream>>>(grids, map, src);
-  return hipGetLastError();
-}
 
 hipError_t launch_blur_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
                              int waves_per_block, int state_idx, int vertical, hipStream_t stream) {

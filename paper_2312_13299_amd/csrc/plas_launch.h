@@ -43,10 +43,25 @@ hipError_t launch_check_perm(const int32_t* init, int64_t n, int32_t* counts, in
 // G[p] = X[P[p]] over dp channels (P NULL: identity).
 hipError_t launch_gather(const void* X, const int32_t* P, void* G, int64_t n, int dp, int storage,
                          hipStream_t stream);
-// One blur pass (vertical = 0: rows, 1: columns) with the radius of st->r,
-// or `radius` if st is NULL. inv: float32 1/c for c = 0..w.
+// The controller step a row pass runs first: the control step of the
+// reorder that ran on `in` (its energy, the stall test, the schedule),
+// written to `out` (a different state buffer), and the grouping table of the
+// coming reorder; the pass then blurs with `out`'s radius.
+struct StepArgs {
+  const DevState* in;
+  DevState* out;
+  const LevelInfo* levels;
+  plas_level_out* trace;
+  int32_t* table;
+  int64_t table_cells;  // largest beta^2 of the sort: the pass launches enough blocks to fill it quickly
+};
+
+// One blur pass (vertical = 0: rows, 1: columns). Its radius: after the
+// step when step is given (rows), else st->r, or `radius` if st is NULL.
+// inv: float32 1/c for c = 0..w.
 hipError_t launch_blur_pass(const void* in, void* out, int w, int dp, int storage, const DevState* st,
-                            int radius, int vertical, const float* inv, hipStream_t stream);
+                            int radius, int vertical, const float* inv, hipStream_t stream,
+                            const StepArgs* step = nullptr);
 // Grouping table of the current reorder: table[t] = packed pi(t), t < beta^2.
 hipError_t launch_group_table(int32_t* table, const DevState* st, int64_t max_cells,
                               hipStream_t stream);
@@ -54,11 +69,6 @@ hipError_t launch_group_table(int32_t* table, const DevState* st, int64_t max_ce
 // groups + singles over every level this launch may see.
 hipError_t launch_assign(void* G, const void* T, int32_t* P, const int32_t* table, DevState* st, int dp,
                          int storage, int64_t max_items, hipStream_t stream);
-// Between reorders: the control step of the reorder that ran on `in` (its
-// energy, the stall test, the schedule) written to `out`, and the grouping
-// table of the next reorder. in and out are two different state buffers.
-hipError_t launch_step(const DevState* in, DevState* out, const LevelInfo* levels, plas_level_out* trace,
-                       int32_t* table, int64_t max_cells, hipStream_t stream);
 // VAD (App. C) of features[perm] on a w x w grid: out[0] receives the mean
 // |a - b| over neighbour pairs and channels, out[1] the variance. part:
 // device scratch of vad_partial_doubles() doubles; out: device double[2].
@@ -70,15 +80,15 @@ hipError_t launch_vad(const void* features, int input_bf16, const int32_t* perm,
 // (device uint32[blocks]) holds (grid index << 16) | block index within the
 // grid's blocks; a grid's entries run from 0 to its block count - 1.
 // Blocks each grid takes per launch kind.
-int batch_step_blocks(int64_t max_cells);
-int batch_blur_blocks(int w, int dp, int waves_per_block);  // waves_per_block: 1, 2, 4 (dp == 64 only)
+// Blur blocks: enough for every line, and for filling a grouping table of
+// max_cells entries at about one entry per thread.
+int batch_blur_blocks(int w, int dp, int waves_per_block, int64_t max_cells);  // waves_per_block: 1, 2, 4 (dp 64)
 int batch_assign_blocks(int64_t max_items, int dp, int cap);  // cap <= 0: the single-sort default
 int default_assign_blocks_cap();
-// Step of every mapped grid: reads states[src], writes states[src ^ 1].
-hipError_t launch_step_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int src,
-                             hipStream_t stream);
 // One blur pass (vertical 0: G -> H, 1: H -> T) of every mapped grid, all of
-// dp channels and `storage`, with states[state_idx].
+// dp channels and `storage`, with states[state_idx]; the row pass first
+// steps each grid's controller from states[state_idx ^ 1] to
+// states[state_idx] and fills its grouping table.
 hipError_t launch_blur_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
                              int waves_per_block, int state_idx, int vertical, hipStream_t stream);
 hipError_t launch_assign_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,

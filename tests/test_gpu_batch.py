@@ -145,7 +145,8 @@ def test_profile_and_stats(env):
     feats = [torch.from_numpy(synthetic.gaussian_attributes(s * s, s)).cuda() for s in sides]
     perms, results, b = ctx.sort_batch(feats, sides=sides, seeds=[1, 2], profile=True, graph=True)
     assert b.graph_builds == 0  # profiling runs direct launches
-    assert b.step_ms > 0 and b.blur_ms > 0 and b.assign_ms > 0
+    # The controller step runs inside the row blur: no time of its own.
+    assert b.step_ms >= 0 and b.blur_ms > 0 and b.assign_ms > 0
     assert b.chunks >= 1 and b.reorder_slots == 32 * b.chunks
     assert max(r.total_ms for r in results) <= b.total_ms + 1e-6
     for f, s, seed, perm, res in zip(feats, sides, [1, 2], perms, results):
