@@ -634,10 +634,13 @@ int32_t plas_sort_batch(plas_handle h, const plas_batch_item* items, int32_t cou
   plas_batch_config cfg;
   st = check_config(h, config, &cfg);
   if (st != PLAS_OK) return st;
-  for (int32_t i = 0; i < count; ++i)
-    for (int32_t j = 0; j < i; ++j)
-      if (items[i].perm_out == items[j].perm_out)
-        return fail(h, PLAS_ERR_INVALID_ARGUMENT, "items share a perm_out buffer");
+  {
+    std::vector<const void*> outs(static_cast<size_t>(count));
+    for (int32_t i = 0; i < count; ++i) outs[i] = items[i].perm_out;
+    std::sort(outs.begin(), outs.end());
+    if (std::adjacent_find(outs.begin(), outs.end()) != outs.end())
+      return fail(h, PLAS_ERR_INVALID_ARGUMENT, "items share a perm_out buffer");
+  }
   DeviceScope scope(h->device);
   if (!scope.ok()) return fail(h, PLAS_ERR_HIP, "hipSetDevice failed");
   st = ensure_batch_state(h);
