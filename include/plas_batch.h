@@ -52,7 +52,8 @@ typedef struct {
 typedef struct {
     int32_t side_lo;
     int32_t side_hi;
-    int32_t blur_waves_per_block; /* 64-channel blur: lines (one per wave) per block, 1, 2 or 4; 0: 2 */
+    int32_t blur_waves_per_block; /* staged blur (cells of 16 bytes or more): waves per block, each
+                                     walking 64/dp lines; 1, 2 or 4; 0: 2 */
     int32_t assign_blocks;        /* blocks per sort for the assignment; 0: the plas_sort default */
 } plas_tune_entry;
 
@@ -107,7 +108,7 @@ int32_t plas_sort_batch(plas_handle h, const plas_batch_item* items, int32_t cou
  * are grouped into side buckets [ceil(2^(b/2)), ceil(2^((b+1)/2)) - 1]; for
  * each bucket, truncated batch sorts of its items (6 reorders at the first,
  * coarsest level and 6 at radius 15) are timed under each candidate blur
- * shape (1, 2, 4 lines per block, 64-channel grids only) and then each
+ * shape (1, 2, 4 waves per block, grids with cells of 16 bytes or more) and then each
  * candidate assignment block count (default, 256, 1024, 16384), keeping the
  * fastest. graph: as in plas_batch_config. table: host array of cap entries;
  * *entries receives the number written. The items' perm_out contents are

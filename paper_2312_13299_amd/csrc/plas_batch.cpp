@@ -91,6 +91,10 @@ struct Sort {
   int64_t footprint = 0;
 };
 
+// Lines per block of a sort's blur launches (0 for the register kernel,
+// which has one fixed shape).
+int blur_wpb(const Sort& s) { return plas::staged_blur(s.dp, s.storage) ? s.wpb : 0; }
+
 }  // namespace
 
 struct plas_batch_state {
@@ -257,7 +261,7 @@ class BatchRun {
     g.trace = reinterpret_cast<plas_level_out*>(base + o_trace);
     g.states = reinterpret_cast<DevState*>(base + o_states);
     g.w = s.w;
-    g.blur_blocks = plas::batch_blur_blocks(s.w, s.dp, s.wpb, s.max_cells);
+    g.blur_blocks = plas::batch_blur_blocks(s.w, s.dp, s.storage, s.wpb, s.max_cells);
     g.assign_blocks = plas::batch_assign_blocks(s.max_items, s.dp, s.assign_cap);
 
     // Features -> X in T, the start arrangement, G = X[P] (as plas_sort).
@@ -468,14 +472,14 @@ class BatchRun {
       std::vector<std::array<int, 3>> keys;
       for (int slot : run_list_) {
         const Sort& s = sorts_[slot];
-        const std::array<int, 3> k = {s.dp, s.storage, pass == 0 ? (s.dp == 64 ? s.wpb : 0) : 0};
+        const std::array<int, 3> k = {s.dp, s.storage, pass == 0 ? blur_wpb(s) : 0};
         if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
       }
       for (const auto& k : keys) {
         std::vector<int> members;
         for (int slot : run_list_) {
           const Sort& s = sorts_[slot];
-          if (s.dp == k[0] && s.storage == k[1] && (pass == 1 || (s.dp == 64 ? s.wpb : 0) == k[2]))
+          if (s.dp == k[0] && s.storage == k[1] && (pass == 1 || blur_wpb(s) == k[2]))
             members.push_back(slot);
         }
         add_launch(pass == 0 ? kBlur : kAssign, k[0], k[1], k[2], members);
@@ -682,13 +686,13 @@ int32_t plas_autotune_batch(plas_handle h, const plas_batch_item* items, int32_t
   fine.start_radius = 15.0;
   for (int b : buckets) {
     std::vector<plas_batch_item> sub;
-    bool has64 = false;
+    bool staged = false;
     for (int32_t i = 0; i < count; ++i)
       if (side_bucket(std::max(2, items[i].side)) == b) {
         plas_batch_item it = items[i];
         it.stats = nullptr;
         sub.push_back(it);
-        has64 = has64 || padded_channels(it.d) == 64;
+        staged = staged || plas::staged_blur(padded_channels(it.d), it.storage);
       }
     plas_tune_entry e{};
     e.side_lo = static_cast<int32_t>(std::ceil(std::pow(2.0, b / 2.0)));
@@ -723,7 +727,7 @@ int32_t plas_autotune_batch(plas_handle h, const plas_batch_item* items, int32_t
     e.blur_waves_per_block = kDefaultWavesPerBlock;
     e.assign_blocks = 0;
     for (int wpb : {2, 1, 4}) {
-      if (!has64 && wpb != kDefaultWavesPerBlock) continue;
+      if (!staged && wpb != kDefaultWavesPerBlock) continue;
       plas_tune_entry cand = e;
       cand.blur_waves_per_block = wpb;
       double ms = 0.0;

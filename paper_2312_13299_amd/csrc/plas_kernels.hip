@@ -492,14 +492,25 @@ struct StagedRegs {
   float mult;  // lane p < kChunk: float32(1/count) of the chunk's position p
 };
 
-template <typename S>
+// A wave walks 64 / DP lines side by side (DP = 64: one line). LDS row p
+// holds position p of all of them: element l * DP + c is channel c of line
+// l, and lane l * DP + c runs that chain. For the memory side, the row is cut
+// into 16-byte pieces; load lane (q, j) moves piece j of position q of each
+// group of kPos positions, and piece j belongs to line j / kPiecesPerCell.
+template <typename S, int DP>
 struct StagedLine {
   using Shape = StagedShape<S>;
   static constexpr int kChunk = Shape::kChunk;
-  const S* __restrict__ src;
-  S* __restrict__ dst;
+  static constexpr int kPiecesPerCell = DP * static_cast<int>(sizeof(S)) / 16;
+  static_assert(kPiecesPerCell >= 1, "a cell must hold at least one 16-byte piece");
+  const S* __restrict__ src;  // the pass's input grid
+  S* __restrict__ dst;        // and output grid
   const float* __restrict__ inv;
-  int64_t step;
+  int64_t step;    // elements between consecutive positions of a line
+  int64_t ld_off;  // element offset of this lane's load piece at position 0
+  int64_t own_off; // element offset of this lane's chain at position 0
+  bool ld_ok;      // the load piece's line exists (else its loads are clamped and its stores skipped)
+  bool own_ok;     // this lane's chain line exists
   int w, r, first_hi, n_init, n_chunks;
   int q, j, lane;
   StagedLds<S>* lds;
@@ -507,7 +518,7 @@ struct StagedLine {
   __device__ __forceinline__ int clamp_pos(int t) const { return t < 0 ? 0 : (t > w - 1 ? w - 1 : t); }
 
   __device__ __forceinline__ uint4 ld(int t) const {
-    return reinterpret_cast<const uint4*>(src + static_cast<int64_t>(t) * step)[j];
+    return *reinterpret_cast<const uint4*>(src + ld_off + static_cast<int64_t>(t) * step);
   }
 
   // Chunks 0 .. n_init-1 cover positions 0 .. first_hi of the starting sum
@@ -519,13 +530,13 @@ struct StagedLine {
     if (!init && base - r - 1 >= 0 && base + kChunk - 1 + r <= w - 1) {
       // Every entering and leaving position of the chunk lies in the line:
       // walk both streams with one pointer step per load.
-      const uint4* pe = reinterpret_cast<const uint4*>(src + static_cast<int64_t>(base + r + q) * step) + j;
-      const uint4* pl = reinterpret_cast<const uint4*>(src + static_cast<int64_t>(base - r - 1 + q) * step) + j;
-      const int64_t inc = static_cast<int64_t>(Shape::kPos) * step * static_cast<int64_t>(sizeof(S)) / 16;
+      const S* pe = src + ld_off + static_cast<int64_t>(base + r + q) * step;
+      const S* pl = src + ld_off + static_cast<int64_t>(base - r - 1 + q) * step;
+      const int64_t inc = static_cast<int64_t>(Shape::kPos) * step;
 #pragma unroll
       for (int i = 0; i < Shape::kVec; ++i) {
-        R.enter[i] = pe[i * inc];
-        R.leave[i] = pl[i * inc];
+        R.enter[i] = *reinterpret_cast<const uint4*>(pe + i * inc);
+        R.leave[i] = *reinterpret_cast<const uint4*>(pl + i * inc);
       }
     } else {
 #pragma unroll
@@ -623,8 +634,8 @@ struct StagedLine {
           }
         }
       }
-      if (c == n_init - 1)
-        dst[lane] = Storage<S>::narrow(s * __int_as_float(__builtin_amdgcn_readfirstlane(mult_bits)));
+      if (c == n_init - 1 && own_ok)
+        dst[own_off] = Storage<S>::narrow(s * __int_as_float(__builtin_amdgcn_readfirstlane(mult_bits)));
       return;
     }
     const int x0c = 1 + (c - n_init) * kChunk;
@@ -651,32 +662,42 @@ struct StagedLine {
 #pragma unroll
     for (int i = 0; i < Shape::kVec; ++i) {
       const int x = x0c + Shape::kPos * i + q;
-      if (x < w)
-        reinterpret_cast<uint4*>(dst + static_cast<int64_t>(x) * step)[j] =
+      if (x < w && ld_ok)
+        *reinterpret_cast<uint4*>(dst + ld_off + static_cast<int64_t>(x) * step) =
             *reinterpret_cast<const uint4*>(&lds->out[Shape::kPos * i + q][Shape::kChannels * j]);
     }
   }
 };
 
-// One line of a staged blur pass, by one wave.
-template <typename S>
+// Lines line0 .. line0 + 64/DP - 1 of a staged blur pass (those below w),
+// by one wave.
+template <typename S, int DP>
 __device__ __forceinline__ void blur_staged_line(const S* __restrict__ in, S* __restrict__ out, int w, int r,
-                                                 int vertical, const float* __restrict__ inv, int64_t line,
+                                                 int vertical, const float* __restrict__ inv, int64_t line0,
                                                  int lane, StagedLds<S>* lds) {
-  StagedLine<S> L;
-  const int64_t base = vertical ? line * 64 : line * w * 64;
-  L.src = in + base;
-  L.dst = out + base;
+  using L_t = StagedLine<S, DP>;
+  L_t L;
+  // Element offset of line l at position 0, and between positions.
+  auto line_off = [&](int64_t l) { return vertical ? l * DP : l * w * DP; };
+  L.src = in;
+  L.dst = out;
   L.inv = inv;
-  L.step = vertical ? static_cast<int64_t>(w) * 64 : 64;
+  L.step = vertical ? static_cast<int64_t>(w) * DP : DP;
   L.w = w;
   L.r = r;
   L.q = lane / StagedShape<S>::kLanesPerCell;
   L.j = lane % StagedShape<S>::kLanesPerCell;
+  const int64_t ld_line = line0 + L.j / L_t::kPiecesPerCell;
+  L.ld_ok = ld_line < w;
+  L.ld_off = line_off(L.ld_ok ? ld_line : w - 1) + (L.j % L_t::kPiecesPerCell) * StagedShape<S>::kChannels;
+  const int64_t own_line = line0 + lane / DP;
+  L.own_ok = own_line < w;
+  L.own_off = line_off(L.own_ok ? own_line : w - 1) + lane % DP;
   L.lane = lane;
   L.lds = lds;
   if (r == 0) {
-    for (int x = 0; x < w; ++x) L.dst[x * L.step + lane] = L.src[x * L.step + lane];
+    if (L.own_ok)
+      for (int x = 0; x < w; ++x) L.dst[L.own_off + x * L.step] = L.src[L.own_off + x * L.step];
     return;
   }
   constexpr int kChunk = StagedShape<S>::kChunk;
@@ -694,29 +715,44 @@ __device__ __forceinline__ void blur_staged_line(const S* __restrict__ in, S* __
   }
 }
 
-// One wave per line, WPB waves per block: block `bid` of `nblocks` takes
-// lines bid * WPB + wave, and walks on with a stride if there are more lines
-// than waves.
-template <typename S, int WPB>
+// One group of 64/DP lines per wave, WPB waves per block: block `bid` of
+// `nblocks` takes groups bid * WPB + wave, and walks on with a stride if
+// there are more groups than waves.
+template <typename S, int DP, int WPB>
 __device__ __forceinline__ void blur_staged_lines(const S* __restrict__ in, S* __restrict__ out, int w, int r,
                                                   int vertical, const float* __restrict__ inv, int64_t bid,
                                                   int64_t nblocks, StagedLds<S>* stage) {
+  constexpr int kLinesPerWave = 64 / DP;
   const int wib = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  for (int64_t line = bid * WPB + wib; line < w; line += nblocks * WPB)
-    blur_staged_line<S>(in, out, w, r, vertical, inv, line, lane, stage + wib);
+  for (int64_t g = bid * WPB + wib; g * kLinesPerWave < w; g += nblocks * WPB)
+    blur_staged_line<S, DP>(in, out, w, r, vertical, inv, g * kLinesPerWave, lane, stage + wib);
 }
 
-template <typename S, int WPB>
-__global__ __launch_bounds__(WPB * 64) void k_blur_staged64(const S* __restrict__ in, S* __restrict__ out, int w,
-                                                            const DevState* __restrict__ st, int radius,
-                                                            int vertical, const float* __restrict__ inv,
-                                                            StepArgs step) {
+// Staged blur pass for cells of at least 16 bytes (DP * sizeof(S) >= 16).
+template <typename S, int DP, int WPB>
+__global__ __launch_bounds__(WPB * 64) void k_blur_staged(const S* __restrict__ in, S* __restrict__ out, int w,
+                                                          const DevState* __restrict__ st, int radius,
+                                                          int vertical, const float* __restrict__ inv,
+                                                          StepArgs step) {
   __shared__ StagedLds<S> s_stage[WPB];
   __shared__ DevState s_st;
   int r;
   if (!pass_radius<WPB * 64>(step, st, radius, blockIdx.x, gridDim.x, s_st, r)) return;
-  blur_staged_lines<S, WPB>(in, out, w, r, vertical, inv, blockIdx.x, gridDim.x, s_stage);
+  blur_staged_lines<S, DP, WPB>(in, out, w, r, vertical, inv, blockIdx.x, gridDim.x, s_stage);
+}
+
+// Cells of DP * sizeof(S) bytes are moved in 16-byte pieces when they hold
+// at least one (every float32 width, bfloat16 from 8 channels up).
+template <typename S, int DP>
+constexpr bool staged_cells() {
+  return DP * static_cast<int>(sizeof(S)) >= 16;
+}
+
+// Wave groups (of 64/DP lines) of a staged pass over w lines.
+template <int DP>
+inline int64_t staged_groups(int w) {
+  return (w + 64 / DP - 1) / (64 / DP);
 }
 
 // ---------------------------------------------------------- group table
@@ -1340,10 +1376,10 @@ __device__ __forceinline__ StepArgs batch_step(const BatchGridView& g, int state
   return a;
 }
 
-template <typename S, int WPB>
-__global__ __launch_bounds__(WPB * 64) void k_blur_staged64_batch(const BatchGrid* __restrict__ grids,
-                                                                  const uint32_t* __restrict__ map,
-                                                                  int state_idx, int vertical) {
+template <typename S, int DP, int WPB>
+__global__ __launch_bounds__(WPB * 64) void k_blur_staged_batch(const BatchGrid* __restrict__ grids,
+                                                                const uint32_t* __restrict__ map,
+                                                                int state_idx, int vertical) {
   __shared__ StagedLds<S> s_stage[WPB];
   __shared__ DevState s_st;
   uint32_t local;
@@ -1354,7 +1390,8 @@ __global__ __launch_bounds__(WPB * 64) void k_blur_staged64_batch(const BatchGri
     return;
   const S* in = global_ptr<const S>(vertical ? g.H : g.G);
   S* out = global_ptr<S>(vertical ? g.T : g.H);
-  blur_staged_lines<S, WPB>(in, out, g.w, r, vertical, global_ptr<const float>(g.inv), local, g.blur_blocks, s_stage);
+  blur_staged_lines<S, DP, WPB>(in, out, g.w, r, vertical, global_ptr<const float>(g.inv), local, g.blur_blocks,
+                                s_stage);
 }
 
 template <int DP, typename S>
@@ -1493,32 +1530,38 @@ hipError_t launch_gather(const void* X, const int32_t* P, void* G, int64_t n, in
   return hipGetLastError();
 }
 
-hipError_t launch_blur_pass(const void* in, void* out, int w, int dp, int storage, const DevState* st,
-                            int radius, int vertical, const float* inv, hipStream_t stream, const StepArgs* step) {
-  const StepArgs sa = step != nullptr ? *step : StepArgs{};
+// One pass for storage S and DP channels: the staged kernel when cells
+// hold whole 16-byte pieces, else the register kernel.
+template <typename S, int DP>
+hipError_t blur_pass_dp(const void* in, void* out, int w, const DevState* st, int radius, int vertical,
+                        const float* inv, hipStream_t stream, const StepArgs& sa) {
   // With the step, also enough blocks to fill the grouping table at about
   // one entry per thread (blocks beyond the lines only do that).
-  auto with_table = [&](int blocks, int threads) {
-    if (sa.in == nullptr) return blocks;
+  auto with_table = [&](int64_t blocks, int threads) {
+    if (sa.in == nullptr) return static_cast<int>(blocks);
     const int64_t need = std::min<int64_t>(1024, (sa.table_cells + threads - 1) / threads);
     return static_cast<int>(std::max<int64_t>(blocks, need));
   };
-  if (dp == 64) {
-    const int blocks = with_table((w + kBlurWavesPerBlock - 1) / kBlurWavesPerBlock, kBlurWavesPerBlock * 64);
-    PLAS_DISPATCH_STORAGE(storage, {
-      k_blur_staged64<SV, kBlurWavesPerBlock><<<blocks, kBlurWavesPerBlock * 64, 0, stream>>>(
-          static_cast<const SV*>(in), static_cast<SV*>(out), w, st, radius, vertical, inv, sa);
-    });
-    return hipGetLastError();
+  if constexpr (staged_cells<S, DP>()) {
+    constexpr int kThreads = kBlurWavesPerBlock * 64;
+    const int blocks = with_table((staged_groups<DP>(w) + kBlurWavesPerBlock - 1) / kBlurWavesPerBlock, kThreads);
+    k_blur_staged<S, DP, kBlurWavesPerBlock><<<blocks, kThreads, 0, stream>>>(
+        static_cast<const S*>(in), static_cast<S*>(out), w, st, radius, vertical, inv, sa);
+  } else {
+    const int blocks = with_table((blur_reg_waves<DP>(w) + kWavesPerBlock - 1) / kWavesPerBlock, kBlock);
+    k_blur<DP, S><<<blocks, kBlock, 0, stream>>>(static_cast<const S*>(in), static_cast<S*>(out), w, st, radius,
+                                                 vertical, inv, sa);
   }
-  int64_t waves = 0;
-  PLAS_DISPATCH_DP(dp, waves = blur_reg_waves<DPV>(w));
-  const int blocks = with_table(static_cast<int>((waves + kWavesPerBlock - 1) / kWavesPerBlock), kBlock);
-  PLAS_DISPATCH_STORAGE(storage, {
-    PLAS_DISPATCH_DP(dp, (k_blur<DPV, SV><<<blocks, kBlock, 0, stream>>>(
-                             static_cast<const SV*>(in), static_cast<SV*>(out), w, st, radius, vertical, inv, sa)));
-  });
   return hipGetLastError();
+}
+
+hipError_t launch_blur_pass(const void* in, void* out, int w, int dp, int storage, const DevState* st,
+                            int radius, int vertical, const float* inv, hipStream_t stream, const StepArgs* step) {
+  const StepArgs sa = step != nullptr ? *step : StepArgs{};
+  PLAS_DISPATCH_STORAGE(storage, {
+    PLAS_DISPATCH_DP(dp, return (blur_pass_dp<SV, DPV>(in, out, w, st, radius, vertical, inv, stream, sa)));
+  });
+  return hipSuccess;
 }
 
 hipError_t launch_group_table(int32_t* table, const DevState* st, int64_t max_cells,
@@ -1575,19 +1618,22 @@ hipError_t launch_vad(const void* features, int input_bf16, const int32_t* perm,
 
 // ---- batch
 
-int batch_blur_blocks(int w, int dp, int waves_per_block, int64_t max_cells) {
+bool staged_blur(int dp, int storage) { return dp * (storage == kStorageBF16 ? 2 : 4) >= 16; }
+
+int batch_blur_blocks(int w, int dp, int storage, int waves_per_block, int64_t max_cells) {
   int64_t blocks = 0, threads = 0;
-  if (dp == 64) {
-    blocks = (w + waves_per_block - 1) / waves_per_block;
+  int64_t groups = 0, waves = 0;
+  switch (dp) {
+    case 4: groups = staged_groups<4>(w); waves = blur_reg_waves<4>(w); break;
+    case 8: groups = staged_groups<8>(w); waves = blur_reg_waves<8>(w); break;
+    case 16: groups = staged_groups<16>(w); waves = blur_reg_waves<16>(w); break;
+    case 32: groups = staged_groups<32>(w); waves = blur_reg_waves<32>(w); break;
+    default: groups = staged_groups<64>(w); waves = blur_reg_waves<64>(w); break;
+  }
+  if (staged_blur(dp, storage)) {
+    blocks = (groups + waves_per_block - 1) / waves_per_block;
     threads = 64 * waves_per_block;
   } else {
-    int64_t waves = 0;
-    switch (dp) {
-      case 4: waves = blur_reg_waves<4>(w); break;
-      case 8: waves = blur_reg_waves<8>(w); break;
-      case 16: waves = blur_reg_waves<16>(w); break;
-      default: waves = blur_reg_waves<32>(w); break;
-    }
     blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
     threads = kBlock;
   }
@@ -1603,30 +1649,36 @@ int batch_assign_blocks(int64_t max_items, int dp, int cap) {
 
 int default_assign_blocks_cap() { return PLAS_ASSIGN_MAX_BLOCKS; }
 
+template <typename S, int DP>
+hipError_t blur_batch_dp(const BatchGrid* grids, const uint32_t* map, int blocks, int waves_per_block,
+                         int state_idx, int vertical, hipStream_t stream) {
+  if constexpr (staged_cells<S, DP>()) {
+    switch (waves_per_block) {
+      case 1:
+        k_blur_staged_batch<S, DP, 1><<<blocks, 64, 0, stream>>>(grids, map, state_idx, vertical);
+        break;
+      case 2:
+        k_blur_staged_batch<S, DP, 2><<<blocks, 128, 0, stream>>>(grids, map, state_idx, vertical);
+        break;
+      case 4:
+        k_blur_staged_batch<S, DP, 4><<<blocks, 256, 0, stream>>>(grids, map, state_idx, vertical);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
+  } else {
+    k_blur_batch<DP, S><<<blocks, kBlock, 0, stream>>>(grids, map, state_idx, vertical);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_blur_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
                              int waves_per_block, int state_idx, int vertical, hipStream_t stream) {
-  if (dp == 64) {
-    PLAS_DISPATCH_STORAGE(storage, {
-      switch (waves_per_block) {
-        case 1:
-          k_blur_staged64_batch<SV, 1><<<blocks, 64, 0, stream>>>(grids, map, state_idx, vertical);
-          break;
-        case 2:
-          k_blur_staged64_batch<SV, 2><<<blocks, 128, 0, stream>>>(grids, map, state_idx, vertical);
-          break;
-        case 4:
-          k_blur_staged64_batch<SV, 4><<<blocks, 256, 0, stream>>>(grids, map, state_idx, vertical);
-          break;
-        default:
-          return hipErrorInvalidValue;
-      }
-    });
-    return hipGetLastError();
-  }
   PLAS_DISPATCH_STORAGE(storage, {
-    PLAS_DISPATCH_DP(dp, (k_blur_batch<DPV, SV><<<blocks, kBlock, 0, stream>>>(grids, map, state_idx, vertical)));
+    PLAS_DISPATCH_DP(dp, return (blur_batch_dp<SV, DPV>(grids, map, blocks, waves_per_block, state_idx, vertical,
+                                                        stream)));
   });
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t launch_assign_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,

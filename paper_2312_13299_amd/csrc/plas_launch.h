@@ -80,9 +80,12 @@ hipError_t launch_vad(const void* features, int input_bf16, const int32_t* perm,
 // (device uint32[blocks]) holds (grid index << 16) | block index within the
 // grid's blocks; a grid's entries run from 0 to its block count - 1.
 // Blocks each grid takes per launch kind.
+// Whether blur passes of this shape use the staged kernel (cells of at
+// least 16 bytes); waves_per_block applies to those only.
+bool staged_blur(int dp, int storage);
 // Blur blocks: enough for every line, and for filling a grouping table of
 // max_cells entries at about one entry per thread.
-int batch_blur_blocks(int w, int dp, int waves_per_block, int64_t max_cells);  // waves_per_block: 1, 2, 4 (dp 64)
+int batch_blur_blocks(int w, int dp, int storage, int waves_per_block, int64_t max_cells);  // wpb: 1, 2, 4
 int batch_assign_blocks(int64_t max_items, int dp, int cap);  // cap <= 0: the single-sort default
 int default_assign_blocks_cap();
 // One blur pass (vertical 0: G -> H, 1: H -> T) of every mapped grid, all of
