@@ -47,8 +47,8 @@
 
 /* ------------------------------------------------------------------------ */
 /* Random numbers: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel      */
-/* Random Numbers: As Easy as 1, 2, 3", SC'11). The paper only says          */
-/* "random" (Sec. 3.1); a counter-based generator lets every draw be named   */
+/* Random Numbers: As Easy as 1, 2, 3", SC'11). The paper does not name a   */
+/* generator (Sec. 3.1); a counter-based one lets every draw be named        */
 /* by (seed, purpose, index). Pinned against numpy.random.Philox.            */
 /* ------------------------------------------------------------------------ */
 
@@ -112,11 +112,12 @@ uint64_t plas_ref_fmix64(uint64_t k)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Random permutations. "The groups of four are chosen from a random         */
-/* permutation of all elements from a block" (Sec. 3.1, Blockwise Linear     */
-/* Assignment); the start is "random positions" (Sec. 3.1). Reading: a keyed */
-/* bijection of [0, n) evaluated per element: a balanced 4-round Feistel     */
-/* network on 2h bits, h = max(1, ceil(ceil(log2 n) / 2)), round function    */
+/* Random permutations. Each block's elements are split into groups of four */
+/* along one random permutation of the block (Sec. 3.1, Blockwise Linear     */
+/* Assignment), and the sort starts from a random arrangement (Sec. 3.1).    */
+/* Reading: a keyed bijection of [0, n) evaluated per element: a balanced    */
+/* 4-round Feistel network on 2h bits, h = max(1, ceil(ceil(log2 n) / 2)),   */
+/* round function                                                            */
 /* F(R, K) = fmix64(R xor K) mod 2^h, and cycle walking (Black and Rogaway,  */
 /* "Ciphers with Arbitrary Finite Domains", 2002) down to [0, n).            */
 /* Pinned: bijective for every n up to 2^12 and sampled larger n; key        */
@@ -163,7 +164,8 @@ void plas_ref_bijection_table(uint64_t n, const uint64_t rk[4], int64_t* out)
         out[i] = (int64_t)plas_ref_bijection(n, rk, (uint64_t)i);
 }
 
-/* "we shift all blocks by a random dy and dx" (Sec. 3.1). Reading: a torus
+/* All blocks move together by one random offset (dy, dx) per draw (Sec.
+ * 3.1). Reading: a torus
  * roll with dy, dx uniform in [0, w), taken from the top 32 bits of the first
  * two words of the shift draw: (hi32 * w) >> 32. */
 void plas_ref_shift(uint64_t seed, uint64_t j, int32_t w, int32_t* dy, int32_t* dx)
@@ -343,8 +345,9 @@ int32_t plas_ref_blur_storage(const float* G, float* T, int32_t w, int32_t d, in
 }
 
 /* ------------------------------------------------------------------------ */
-/* Distance. Fig. "swapping_pixels" picks "the lowest total distance",       */
-/* Sec. 3.1 measures "the mean L2 distance". Reading: the squared Euclidean  */
+/* Distance. Each group keeps the ordering with the smallest summed         */
+/* distance (Fig. "swapping_pixels"), and progress is measured by the mean   */
+/* L2 distance to the target (Sec. 3.1). Reading: the squared Euclidean      */
 /* distance, as in linear assignment sorting (Sec. 2.2). Its channel sum is  */
 /* a balanced pairwise tree over the channels padded with zeros to the next  */
 /* power of two m: sum(v[0..m)) = sum(v[0..m/2)) + sum(v[m/2..m)). Each term */
