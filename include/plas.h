@@ -80,7 +80,7 @@ typedef struct {
     int64_t max_reorders;    /* 0: run the whole schedule; > 0: stop after this many reorders */
     const int32_t* init_perm;/* device int32[n] start arrangement (gather form), or NULL for the seeded random start */
     int32_t min_block;       /* smallest block side; 16 */
-    int32_t profile;         /* nonzero: time the blur and assignment kernels with HIP events (fills *_ms in stats) */
+    int32_t profile;         /* nonzero: time the blur and assignment kernels of every 8th reorder with HIP events (fills *_ms and *_launches in stats) */
     int32_t reorders_per_sync; /* reorders queued between checks of the device's done flag; 0: library default */
     int32_t storage;         /* PLAS_STORAGE_F32 (default) or PLAS_STORAGE_BF16 */
 } plas_sort_params;
@@ -106,7 +106,9 @@ typedef struct {
     plas_level_stat* trace; /* caller-owned host array, may be NULL */
     int32_t trace_cap;      /* its capacity */
     int32_t reserved;
-    /* With params->profile: summed device time and launch counts. */
+    /* With params->profile: device time summed over the timed launches (every
+     * 8th reorder; each event costs device time, so not every one is timed),
+     * and how many launches that was. Average = *_ms / *_launches. */
     double blur_ms;         /* both blur passes */
     int64_t blur_launches;  /* passes (two per reorder) */
     double assign_ms;       /* assignment kernel */

@@ -210,13 +210,14 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
       DevState* Sd = &states[cur ^ 1];
       const plas::StepArgs step{&states[cur], Sd, Ld, Td, table, max_cells};
       cur ^= 1;
-      if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 0], h->stream));
+      const bool timed = profile && i % kProfileEvery == 0;
+      if (timed) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 0], h->stream));
       PLAS_HIP(h, plas::launch_blur_pass(G, H, w, dp, storage, nullptr, 0, 0, as<float>(h->inv), h->stream, &step));
       PLAS_HIP(h, plas::launch_blur_pass(H, T, w, dp, storage, Sd, 0, 1, as<float>(h->inv), h->stream));
-      if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 1], h->stream));
-      if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 2], h->stream));
+      if (timed) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 1], h->stream));
+      if (timed) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 2], h->stream));
       PLAS_HIP(h, plas::launch_assign(G, T, P, table, Sd, dp, storage, max_items, h->stream));
-      if (profile) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 3], h->stream));
+      if (timed) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 3], h->stream));
     }
     const int64_t first_slot = slots;
     slots += chunk;
@@ -232,14 +233,14 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
     if (profile) {
       // Slots at or after the end of the sort returned at once.
       const int64_t ran = done ? std::max<int64_t>(0, std::min<int64_t>(chunk, k_now - first_slot)) : chunk;
-      for (int64_t i = 0; i < ran; ++i) {
+      for (int64_t i = 0; i < ran; i += kProfileEvery) {
         float a = 0.0f, b = 0.0f;
         PLAS_HIP(h, hipEventElapsedTime(&a, h->events[4 * i + 0], h->events[4 * i + 1]));
         PLAS_HIP(h, hipEventElapsedTime(&b, h->events[4 * i + 2], h->events[4 * i + 3]));
         blur_ms += a;
         assign_ms += b;
+        ++timed_reorders;
       }
-      timed_reorders += ran;
     }
     if (done) break;
     // Every queued slot but the last has been controlled by now; if k falls

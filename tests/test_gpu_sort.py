@@ -140,7 +140,8 @@ def test_chunking_does_not_change_the_result(env):
     c, rc = ctx.sort(F, side, 4, profile=True)
     assert torch.equal(a, b) and torch.equal(a, c)
     assert ra.reorders == rb.reorders == rc.reorders
-    assert rc.assign_launches == rc.reorders and rc.blur_launches == 2 * rc.reorders
+    # Profiling times every 8th reorder (slots 0, 8, 16, 24 of each chunk of 32).
+    assert rc.assign_launches == (rc.reorders + 7) // 8 and rc.blur_launches == 2 * rc.assign_launches
     assert rc.assign_ms > 0 and rc.blur_ms > 0
 
 
