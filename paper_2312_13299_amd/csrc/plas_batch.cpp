@@ -262,7 +262,7 @@ class BatchRun {
     g.states = reinterpret_cast<DevState*>(base + o_states);
     g.w = s.w;
     g.blur_blocks = plas::batch_blur_blocks(s.w, s.dp, s.storage, s.wpb, s.max_cells);
-    g.assign_blocks = plas::batch_assign_blocks(s.max_items, s.dp, s.assign_cap);
+    g.assign_blocks = plas::batch_assign_blocks(s.max_items, s.dp, s.storage, s.assign_cap);
 
     // Features -> X in T, the start arrangement, G = X[P] (as plas_sort).
     hipStream_t stream = b_->stream;

@@ -49,12 +49,13 @@ inline int blocks_for(int64_t threads, int64_t cap = kMaxGridBlocks) {
 // bfloat16 is the high half of a float32: widening is exact.
 __device__ __forceinline__ float bf16_to_float(uint32_t bits) { return __uint_as_float(bits << 16); }
 
-// Nearest bfloat16, ties to even: add 0x7fff plus the kept part's lowest bit,
-// keep the high half. Infinities and NaNs keep their high half.
+// Nearest bfloat16, ties to even: gfx950 converts in one instruction
+// (v_cvt_pk_bf16_f32). Every finite value and both infinities round as the
+// integer form (add 0x7fff plus the kept part's lowest bit, keep the high
+// half) does; a NaN stays a NaN with its sign, so the quiet NaNs that
+// arithmetic produces keep their high half too.
 __device__ __forceinline__ uint32_t float_to_bf16(float f) {
-  const uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return u >> 16;
-  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+  return __builtin_bit_cast(unsigned short, static_cast<__bf16>(f));
 }
 
 template <typename S>
@@ -834,6 +835,42 @@ __device__ inline float chunk_sq(const float4 a, const float4 b) {
   return (e0 * e0 + e1 * e1) + (e2 * e2 + e3 * e3);
 }
 
+// Channels per lane in the assignment: 8 bfloat16 channels (one 16-byte
+// load) when a cell holds at least 8, else 4 (a float4, or 8 bytes of
+// bfloat16). Eight channels per lane add the tree's third level, (first
+// four) + (last four), inside the lane; the lanes then reduce the rest.
+template <typename S, int DP>
+constexpr int assign_channels() {
+  return (sizeof(S) == 2 && DP >= 8) ? 8 : 4;
+}
+
+template <typename S, int DP>
+struct AssignVec {
+  using Quad = typename Storage<S>::Quad;
+  using T = Quad;
+  __device__ static __forceinline__ float sq(const T& a, const T& b) {
+    return chunk_sq(Storage<S>::widen4(a), Storage<S>::widen4(b));
+  }
+};
+
+template <>
+struct AssignVec<uint16_t, 64> {
+  using T = uint4;
+  __device__ static __forceinline__ float sq(const T& a, const T& b) {
+    const float lo = chunk_sq(Storage<uint16_t>::widen4(make_uint2(a.x, a.y)),
+                              Storage<uint16_t>::widen4(make_uint2(b.x, b.y)));
+    const float hi = chunk_sq(Storage<uint16_t>::widen4(make_uint2(a.z, a.w)),
+                              Storage<uint16_t>::widen4(make_uint2(b.z, b.w)));
+    return lo + hi;
+  }
+};
+template <>
+struct AssignVec<uint16_t, 32> : AssignVec<uint16_t, 64> {};
+template <>
+struct AssignVec<uint16_t, 16> : AssignVec<uint16_t, 64> {};
+template <>
+struct AssignVec<uint16_t, 8> : AssignVec<uint16_t, 64> {};
+
 __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
@@ -856,11 +893,12 @@ __device__ __forceinline__ uint32_t order_code(int m) {
 
 // One reorder's blockwise assignment. Items are the groups of every block
 // (item < groups) followed by the cells in no group (singles), whose
-// distance still counts towards the energy. LG = DP/4 lanes serve one item:
-// lane `sub` holds channels 4*sub .. 4*sub+3 of the item's four grid cells
-// and four target cells and forms all 16 pair partials as the two lowest
-// levels of the channel tree. The rest of the work is split across the LG
-// lanes:
+// distance still counts towards the energy. LG = DP / C lanes serve one
+// item, C = assign_channels<S, DP>() (4, or 8 for bfloat16 cells of 8 or
+// more channels): lane `sub` holds channels C*sub .. C*sub+C-1 of the item's
+// four grid cells and four target cells and forms all 16 pair partials as
+// the lowest levels of the channel tree. The rest of the work is split
+// across the LG lanes:
 //  - a transposed butterfly: at tree level b each lane keeps the pairs whose
 //    bit b matches its own lane bit, adds the partner's partial for them and
 //    hands over the others, so after log2(LG) levels lane L holds the exact
@@ -1030,7 +1068,10 @@ template <int DP, typename S>
 __device__ __forceinline__ void assign_items(S* __restrict__ G, const S* __restrict__ T, int32_t* __restrict__ P,
                                              const int32_t* __restrict__ table, DevState* __restrict__ st,
                                              int64_t bid, int64_t nblocks) {
-  constexpr int LG = DP / 4;
+  using V = AssignVec<S, DP>;
+  using Vec = typename V::T;
+  constexpr int LG = DP / assign_channels<S, DP>();
+  static_assert(sizeof(Vec) * LG == DP * sizeof(S), "lane vectors must tile a cell");
   constexpr int IPW = 64 / LG;
   constexpr int LEVELS = LG == 1 ? 0 : LG == 2 ? 1 : LG == 4 ? 2 : LG == 8 ? 3 : 4;
   constexpr int KEEP = 16 / LG;  // pair distances held per lane after the reduction
@@ -1044,10 +1085,9 @@ __device__ __forceinline__ void assign_items(S* __restrict__ G, const S* __restr
   unsigned long long* q_item = s_q[wib][slot];
   const int64_t wave = (bid * kBlock + threadIdx.x) >> 6;
   const int64_t nwaves = (nblocks * kBlock) >> 6;
-  using Quad = typename Storage<S>::Quad;
-  const Quad* __restrict__ G4 = reinterpret_cast<const Quad*>(G);
-  const Quad* __restrict__ T4 = reinterpret_cast<const Quad*>(T);
-  Quad* __restrict__ Gout = reinterpret_cast<Quad*>(G);
+  const Vec* __restrict__ G4 = reinterpret_cast<const Vec*>(G);
+  const Vec* __restrict__ T4 = reinterpret_cast<const Vec*>(T);
+  Vec* __restrict__ Gout = reinterpret_cast<Vec*>(G);
   unsigned long long e_acc = 0, m_acc = 0;
 
   // Software pipeline: the next item's cells (table reads) are resolved
@@ -1059,7 +1099,7 @@ __device__ __forceinline__ void assign_items(S* __restrict__ G, const S* __restr
     const int64_t item = first + slot;
     const bool active = item < geo.total;
     const bool is_group = item < geo.groups;
-    Quad g[4], tg[4];
+    Vec g[4], tg[4];
     int32_t old_perm[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -1078,18 +1118,10 @@ __device__ __forceinline__ void assign_items(S* __restrict__ G, const S* __restr
 
     // Pair q = 4i + j: grid cell i against target cell j.
     float part[16];
-    {
-      float4 gf[4], tf[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        gf[i] = Storage<S>::widen4(g[i]);
-        tf[i] = Storage<S>::widen4(tg[i]);
-      }
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) part[4 * i + j] = chunk_sq(gf[i], tf[j]);
-    }
+      for (int j = 0; j < 4; ++j) part[4 * i + j] = V::sq(g[i], tg[j]);
     if constexpr (LEVELS > 0) transpose_level<0, 8>(part, sub & 1);
     if constexpr (LEVELS > 1) transpose_level<1, 4>(part, sub & 2);
     if constexpr (LEVELS > 2) transpose_level<2, 2>(part, sub & 4);
@@ -1167,8 +1199,19 @@ __device__ __forceinline__ void assign_items(S* __restrict__ G, const S* __restr
 #define PLAS_ASSIGN_WAVES_PER_EU 4
 #endif
 
+// Occupancy target of the assignment kernels. One wave less per SIMD (more
+// registers per lane) where the default would spill to scratch: 8-channel
+// bfloat16 lanes hold twice the raw cell data, and with one or two lanes
+// per item a lane keeps most of the 16 pair costs and orderings itself.
+template <typename S, int DP>
+constexpr int assign_waves_per_eu() {
+  constexpr int lanes = DP / assign_channels<S, DP>();
+  constexpr bool wide = lanes <= 2 || assign_channels<S, DP>() == 8;
+  return wide && PLAS_ASSIGN_WAVES_PER_EU > 1 ? PLAS_ASSIGN_WAVES_PER_EU - 1 : PLAS_ASSIGN_WAVES_PER_EU;
+}
+
 template <int DP, typename S>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PLAS_ASSIGN_WAVES_PER_EU)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(assign_waves_per_eu<S, DP>())))
 void k_assign(S* __restrict__ G, const S* __restrict__ T,
                                                    int32_t* __restrict__ P,
                                                    const int32_t* __restrict__ table,
@@ -1460,7 +1503,7 @@ __global__ __launch_bounds__(kBlock) void k_blur_batch(const BatchGrid* __restri
 }
 
 template <int DP, typename S>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PLAS_ASSIGN_WAVES_PER_EU)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(assign_waves_per_eu<S, DP>())))
 void k_assign_batch(const BatchGrid* __restrict__ grids,
                                                          const uint32_t* __restrict__ map, int state_idx) {
   uint32_t local;
@@ -1618,9 +1661,16 @@ hipError_t launch_group_table(int32_t* table, const DevState* st, int64_t max_ce
   return hipGetLastError();
 }
 
+// Items per wave of the assignment kernel: 64 lanes over DP / C lanes per
+// item (C from assign_channels).
+inline int64_t assign_items_per_wave(int dp, int storage) {
+  const int c = (storage == kStorageBF16 && dp >= 8) ? 8 : 4;
+  return 64 / (dp / c);
+}
+
 hipError_t launch_assign(void* G, const void* T, int32_t* P, const int32_t* table, DevState* st, int dp,
                          int storage, int64_t max_items, hipStream_t stream) {
-  const int64_t items_per_wave = 64 / (dp / 4);
+  const int64_t items_per_wave = assign_items_per_wave(dp, storage);
   const int64_t waves = (max_items + items_per_wave - 1) / items_per_wave;
   const int blocks = blocks_for(waves * 64, PLAS_ASSIGN_MAX_BLOCKS);
   PLAS_DISPATCH_STORAGE(storage, {
@@ -1689,8 +1739,8 @@ int batch_blur_blocks(int w, int dp, int storage, int waves_per_block, int64_t m
   return static_cast<int>(std::max(blocks, need));
 }
 
-int batch_assign_blocks(int64_t max_items, int dp, int cap) {
-  const int64_t items_per_wave = 64 / (dp / 4);
+int batch_assign_blocks(int64_t max_items, int dp, int storage, int cap) {
+  const int64_t items_per_wave = assign_items_per_wave(dp, storage);
   const int64_t waves = (max_items + items_per_wave - 1) / items_per_wave;
   return blocks_for(waves * 64, cap > 0 ? cap : PLAS_ASSIGN_MAX_BLOCKS);
 }

@@ -86,7 +86,7 @@ bool staged_blur(int dp, int storage);
 // Blur blocks: enough for every line, and for filling a grouping table of
 // max_cells entries at about one entry per thread.
 int batch_blur_blocks(int w, int dp, int storage, int waves_per_block, int64_t max_cells);  // wpb: 1, 2, 4
-int batch_assign_blocks(int64_t max_items, int dp, int cap);  // cap <= 0: the single-sort default
+int batch_assign_blocks(int64_t max_items, int dp, int storage, int cap);  // cap <= 0: the single-sort default
 int default_assign_blocks_cap();
 // One blur pass (vertical 0: G -> H, 1: H -> T) of every mapped grid, all of
 // dp channels and `storage`, with states[state_idx]; the row pass first
