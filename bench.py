@@ -439,6 +439,22 @@ def main() -> int:
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
     }
+    # Practical streaming ceiling, outside the timed region: a device copy of
+    # one working grid's bytes (read + write), timed with HIP events.
+    grid_bytes = n * 64 * (2 if precision else 4)
+    src = torch.empty(grid_bytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * grid_bytes * 10 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del src, dst
+    roof["copy_gbs"] = round(copy_gbs, 1)
+    roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
     ms_per_step = elapsed / args.steps * 1e3
     value = n * args.steps / elapsed
     line = {
