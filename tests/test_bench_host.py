@@ -1,0 +1,78 @@
+"""Host logic of bench.py, on the CPU: the one-GPU refusal, the algorithmic
+byte counts behind the roofline, the committed traffic records, and the
+nearest-rank percentile used for serving latencies."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+class _Res:
+    def __init__(self, reorders, moved_per_level, blur_ms, blur_launches, assign_ms, assign_launches):
+        self.reorders = reorders
+        self.trace = [{"moved": m} for m in moved_per_level]
+        self.blur_ms, self.blur_launches = blur_ms, blur_launches
+        self.assign_ms, self.assign_launches = assign_ms, assign_launches
+
+
+def test_kernel_roofline_bytes_and_rates():
+    n, d = 1024 * 1024, 59
+    # 100 reorders, 2,000,000 cells moved in all; 200 blur launches of 0.1 ms,
+    # 100 assignment launches of 0.2 ms.
+    res = _Res(100, [1_500_000, 500_000], 20.0, 200, 20.0, 100)
+    k = bench.kernel_roofline(res, n, d, 4)
+    blur_bytes = n * 2 * d * 4  # read and write one grid, 59 float32 channels
+    assert k["blur_pass"]["bytes"] == blur_bytes == 494_927_872
+    assert k["blur_pass"]["avg_ms"] == pytest.approx(0.1)
+    assert k["blur_pass"]["gbs"] == pytest.approx(blur_bytes / 1e-4 / 1e9)
+    moved = 2_000_000 / 100
+    assert k["assign"]["moved_per_reorder"] == pytest.approx(moved)
+    assert k["assign"]["bytes"] == pytest.approx(n * 2 * d * 4 + moved * (d * 4 + 8))
+    assert k["assign"]["avg_ms"] == pytest.approx(0.2)
+    # bfloat16 storage halves the bytes per channel.
+    assert bench.kernel_roofline(res, n, d, 2)["blur_pass"]["bytes"] == blur_bytes // 2
+    # No timed launches, no entry.
+    assert bench.kernel_roofline(_Res(0, [], 0.0, 0, 0.0, 0), n, d, 4) == {}
+
+
+def test_committed_traffic_records():
+    for workload in ("sort_1024_d59", "sort_1448_d59_bf16"):
+        path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
+        rec = json.load(open(path))
+        if rec["kernel_source_sha256"] != bench.kernel_source_hash():
+            # Counters taken on other kernel code are not used: bench.py
+            # then reports traffic as null.
+            for kernel in ("blur_pass", "assign"):
+                assert bench.measured_traffic(kernel, workload) is None
+            continue
+        for kernel in ("blur_pass", "assign"):
+            v = bench.measured_traffic(kernel, workload)
+            assert v == rec["kernels"][kernel]["hbm_bytes_per_launch"]
+            # At least the grid bytes a launch must move (N cells of 64
+            # padded channels, read once and written once for the blur).
+            assert v > 0
+    assert bench.measured_traffic("blur_pass", "no_such_workload") is None
+    assert bench.measured_traffic("no_such_kernel", "sort_1024_d59") is None
+
+
+def test_percentile_nearest_rank():
+    v = [5.0, 1.0, 4.0, 2.0, 3.0]
+    assert bench.percentile(v, 50) == 3.0
+    assert bench.percentile(v, 99) == 5.0
+    assert bench.percentile(v, 0) == 1.0
+    assert bench.percentile(list(range(1, 101)), 99) == 99
+    assert bench.percentile([7.0], 50) == 7.0
