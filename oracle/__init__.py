@@ -43,7 +43,13 @@ class _Params(ctypes.Structure):
         ("max_reorders", ctypes.c_int64),
         ("init_perm", ctypes.c_void_p),
         ("storage_bf16", ctypes.c_int32),
+        ("filter", ctypes.c_int32),
     ]
+
+
+# The target's low-pass filter: one box pass per axis, or three (a
+# Gaussian-like filter of variance r(r+1) per axis).
+FILTERS = {"box": 0, "box3": 1}
 
 
 class _Level(ctypes.Structure):
@@ -98,6 +104,8 @@ def lib() -> ctypes.CDLL:
             "plas_ref_blur_storage": (ctypes.c_int32, [vp, vp, ctypes.c_int32, ctypes.c_int32,
                                                        ctypes.c_int32, ctypes.c_int32]),
             "plas_ref_round_bf16": (ctypes.c_float, [ctypes.c_float]),
+            "plas_ref_blur_filter": (ctypes.c_int32, [vp, vp, ctypes.c_int32, ctypes.c_int32,
+                                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
             "plas_ref_grid_energy_storage": (ctypes.c_int32, [vp, vp, ctypes.c_int64, ctypes.c_int32,
                                                               ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                               ctypes.c_int32, u64p, i32p,
@@ -193,13 +201,13 @@ def scale_shift(F: np.ndarray, layout: str = "cn") -> tuple[int, int, float]:
     return int(st), s.value, dmax.value
 
 
-def blur(G: np.ndarray, side: int, r: int, storage_bf16: bool = False) -> np.ndarray:
+def blur(G: np.ndarray, side: int, r: int, storage_bf16: bool = False, filter: str = "box") -> np.ndarray:
     """G is [N][d] (cell-major); returns T [N][d]."""
     G = _f32(G)
     N, d = G.shape
     assert N == side * side
     T = np.empty_like(G)
-    st = lib().plas_ref_blur_storage(_ptr(G), _ptr(T), side, d, r, 1 if storage_bf16 else 0)
+    st = lib().plas_ref_blur_filter(_ptr(G), _ptr(T), side, d, r, 1 if storage_bf16 else 0, FILTERS[filter])
     if st != OK:
         raise ValueError(f"plas_ref_blur failed: {st}")
     return T
@@ -298,13 +306,13 @@ class SortResult:
 def sort(F: np.ndarray, side: int, seed: int, layout: str = "cn", *, radius_decay: float = 0.95,
          inv_threshold: int = 10000, min_block: int = 16, start_radius: float = 0.0,
          max_reorders: int = 0, init_perm: np.ndarray | None = None,
-         energy_cap: int = 0, storage_bf16: bool = False) -> SortResult:
+         energy_cap: int = 0, storage_bf16: bool = False, filter: str = "box") -> SortResult:
     F = _f32(F)
     n, d = _nd(F, layout)
     ip = None if init_perm is None else np.ascontiguousarray(init_perm, dtype=np.int32)
     prm = _Params(seed & 0xFFFFFFFFFFFFFFFF, radius_decay, inv_threshold, min_block,
                   start_radius, max_reorders, None if ip is None else ip.ctypes.data,
-                  1 if storage_bf16 else 0)
+                  1 if storage_bf16 else 0, FILTERS[filter])
     cap = 4096
     trace = (_Level * cap)()
     energies = np.zeros(max(energy_cap, 1), dtype=np.uint64)

@@ -314,32 +314,73 @@ int32_t plas_ref_blur(const float* G, float* T, int32_t w, int32_t d, int32_t r)
 int32_t plas_ref_blur_storage(const float* G, float* T, int32_t w, int32_t d, int32_t r,
                               int32_t storage_bf16)
 {
-    if (G == NULL || T == NULL || w < 1 || d < 1 || r < 0)
+    return plas_ref_blur_filter(G, T, w, d, r, storage_bf16, PLAS_REF_FILTER_BOX);
+}
+
+/* One box pass over every line of one axis: rows (horizontal) or columns. */
+static void box_pass(const float* in, float* out, int32_t w, int32_t d, int32_t r, const float* inv,
+                     int32_t bf16, int vertical)
+{
+    int64_t N = (int64_t)w * w;
+    (void)N;
+#pragma omp parallel for schedule(static) if (N >= PAR_MIN_ITEMS)
+    for (int32_t l = 0; l < w; l++)
+        for (int32_t c = 0; c < d; c++) {
+            if (vertical)
+                box_line(in + (int64_t)l * d + c, (ptrdiff_t)w * d, out + (int64_t)l * d + c, w, r, inv,
+                         bf16);
+            else
+                box_line(in + (int64_t)l * w * d + c, d, out + (int64_t)l * w * d + c, w, r, inv, bf16);
+        }
+}
+
+/* Gaussian-like variant (BOX3): the paper names a Gaussian filter without
+ * its kernel. Repeating a box filter approaches a Gaussian (the sum of
+ * three uniform variables; Wells, "Efficient synthesis of Gaussian filters
+ * by cascaded uniform filters", IEEE TPAMI 1986): three passes of
+ * half-width r per axis give a piecewise-quadratic kernel of support 3r
+ * and variance 3 * r(r+1)/3 = r(r+1) per axis. Rows first, three times,
+ * then columns three times; every pass is the clipped box pass above.
+ * Pinned: the response to a single impulse against the three-fold
+ * convolution of box kernels (interior and at a border), its variance,
+ * r = 0 and constant grids. */
+int32_t plas_ref_blur_filter(const float* G, float* T, int32_t w, int32_t d, int32_t r,
+                             int32_t storage_bf16, int32_t filter)
+{
+    if (G == NULL || T == NULL || w < 1 || d < 1 || r < 0 ||
+        (filter != PLAS_REF_FILTER_BOX && filter != PLAS_REF_FILTER_BOX3))
         return PLAS_REF_INVALID;
+    const int passes = filter == PLAS_REF_FILTER_BOX3 ? 3 : 1;
     int64_t N = (int64_t)w * w;
     float* inv = (float*)malloc(sizeof(float) * (size_t)(w + 1));
-    float* H = (float*)malloc(sizeof(float) * (size_t)(N * d));
-    if (inv == NULL || H == NULL) {
+    float* A = (float*)malloc(sizeof(float) * (size_t)(N * d));
+    float* B = passes > 1 ? (float*)malloc(sizeof(float) * (size_t)(N * d)) : NULL;
+    if (inv == NULL || A == NULL || (passes > 1 && B == NULL)) {
         free(inv);
-        free(H);
+        free(A);
+        free(B);
         return PLAS_REF_INVALID;
     }
     inv[0] = 0.0f;
     for (int32_t c = 1; c <= w; c++)
         inv[c] = 1.0f / (float)c;
-    /* Horizontal pass: every row, every channel. */
-#pragma omp parallel for schedule(static) if (N >= PAR_MIN_ITEMS)
-    for (int32_t y = 0; y < w; y++)
-        for (int32_t c = 0; c < d; c++)
-            box_line(G + (int64_t)y * w * d + c, d, H + (int64_t)y * w * d + c, w, r, inv,
-                     storage_bf16);
-    /* Vertical pass on the result: every column, every channel. */
-#pragma omp parallel for schedule(static) if (N >= PAR_MIN_ITEMS)
-    for (int32_t x = 0; x < w; x++)
-        for (int32_t c = 0; c < d; c++)
-            box_line(H + (int64_t)x * d + c, (ptrdiff_t)w * d, T + (int64_t)x * d + c, w, r, inv,
-                     storage_bf16);
-    free(H);
+    float* bufs[2] = {A, B};
+    const float* src = G;
+    /* Horizontal passes: every row, every channel. */
+    for (int p = 0; p < passes; p++) {
+        float* dst = bufs[p & 1];
+        box_pass(src, dst, w, d, r, inv, storage_bf16, 0);
+        src = dst;
+    }
+    /* Vertical passes on the result: every column, every channel; the last
+     * one writes T. */
+    for (int p = 0; p < passes; p++) {
+        float* dst = p == passes - 1 ? T : bufs[(passes + p) & 1];
+        box_pass(src, dst, w, d, r, inv, storage_bf16, 1);
+        src = dst;
+    }
+    free(B);
+    free(A);
     free(inv);
     return PLAS_REF_OK;
 }
@@ -604,7 +645,7 @@ int32_t plas_ref_sort(const float* F, int64_t n, int32_t d, int32_t side, int32_
         d > PLAS_REF_MAX_D || n != (int64_t)side * side ||
         (layout != PLAS_REF_LAYOUT_CN && layout != PLAS_REF_LAYOUT_NC) ||
         !(prm->radius_decay > 0.0 && prm->radius_decay < 1.0) || prm->inv_threshold < 1 ||
-        prm->min_block < 1)
+        prm->min_block < 1 || (prm->filter != PLAS_REF_FILTER_BOX && prm->filter != PLAS_REF_FILTER_BOX3))
         return PLAS_REF_INVALID;
     const int32_t w = side;
     const int64_t N = n;
@@ -677,7 +718,7 @@ int32_t plas_ref_sort(const float* F, int64_t n, int32_t d, int32_t side, int32_
                 stop = 1;
                 break;
             }
-            plas_ref_blur_storage(G, T, w, d, r, bf16);
+            plas_ref_blur_filter(G, T, w, d, r, bf16, prm->filter);
             uint64_t rk[4];
             plas_ref_draw(prm->seed, 1, (uint64_t)k, rk);
             uint64_t moved = 0;

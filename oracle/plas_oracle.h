@@ -45,7 +45,14 @@ typedef struct {
     int64_t max_reorders;     /* 0: run to the end of the schedule */
     const int32_t* init_perm; /* NULL: random start (Sec. 3.1) */
     int32_t storage_bf16;     /* nonzero: features and blurred grids held in bfloat16 */
+    int32_t filter;           /* PLAS_REF_FILTER_BOX (0) or PLAS_REF_FILTER_BOX3 (1) */
 } plas_ref_params;
+
+/* The low-pass filter of the target. BOX: one box pass per axis. BOX3: the
+ * box pass three times per axis (rows three times, then columns three
+ * times), a Gaussian-like filter of variance r(r+1) per axis. */
+#define PLAS_REF_FILTER_BOX 0
+#define PLAS_REF_FILTER_BOX3 1
 
 typedef struct {
     double phi;
@@ -89,6 +96,10 @@ int32_t plas_ref_blur(const float* G, float* T, int32_t w, int32_t d, int32_t r)
 /* The same, with each pass's output rounded to bfloat16 when storage_bf16. */
 int32_t plas_ref_blur_storage(const float* G, float* T, int32_t w, int32_t d, int32_t r,
                               int32_t storage_bf16);
+/* The same for either filter: BOX3 runs the row pass three times and then
+ * the column pass three times, each pass's output rounded as stored. */
+int32_t plas_ref_blur_filter(const float* G, float* T, int32_t w, int32_t d, int32_t r,
+                             int32_t storage_bf16, int32_t filter);
 /* x rounded to the nearest bfloat16 (ties to even), returned as float. */
 float plas_ref_round_bf16(float x);
 /* Squared L2 distance, pairwise tree over channels padded to a power of two. */

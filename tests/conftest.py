@@ -21,6 +21,10 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def ref():
     import oracle
-    if not os.path.exists(oracle.LIBRARY):
+    # Build on first use, and again when the C source is newer than the
+    # library (a stale oracle would check the GPU against old arithmetic).
+    src = [oracle.SOURCE, os.path.join(os.path.dirname(oracle.SOURCE), "plas_oracle.h")]
+    if not os.path.exists(oracle.LIBRARY) or \
+            os.path.getmtime(oracle.LIBRARY) < max(os.path.getmtime(p) for p in src):
         oracle.build()
     return oracle
