@@ -61,6 +61,16 @@ extern "C" {
 #define PLAS_STORAGE_F32 0
 #define PLAS_STORAGE_BF16 1
 
+/* The target's low-pass filter (Sec. 3.1 names a Gaussian filter of radius
+ * phi without its kernel). PLAS_FILTER_BOX: one box (mean) pass of
+ * half-width r = floor(phi) per axis, the window clipped to the grid.
+ * PLAS_FILTER_BOX3: the same box pass three times per axis, rows then
+ * columns: a Gaussian-like kernel of variance r(r+1) per axis and support
+ * 3r (repeated uniform filters, Wells 1986); three times the blur work.
+ * plas_sort only; batches, servers and the energy query use the box. */
+#define PLAS_FILTER_BOX 0
+#define PLAS_FILTER_BOX3 1
+
 /* Largest channel count d. */
 #define PLAS_MAX_CHANNELS 64
 
@@ -83,6 +93,8 @@ typedef struct {
     int32_t profile;         /* nonzero: time the blur and assignment kernels of every 8th reorder with HIP events (fills *_ms and *_launches in stats) */
     int32_t reorders_per_sync; /* reorders queued between checks of the device's done flag; 0: library default */
     int32_t storage;         /* PLAS_STORAGE_F32 (default) or PLAS_STORAGE_BF16 */
+    int32_t filter;          /* PLAS_FILTER_BOX (default) or PLAS_FILTER_BOX3 */
+    int32_t reserved;        /* 0 */
 } plas_sort_params;
 
 /* One radius level of a finished sort. */

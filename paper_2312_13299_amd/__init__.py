@@ -34,6 +34,7 @@ DTYPE_BF16 = 1
 STORAGE_F32 = 0
 STORAGE_BF16 = 1
 STORAGES = {"f32": STORAGE_F32, "bf16": STORAGE_BF16}
+FILTERS = {"box": 0, "box3": 1}  # PLAS_FILTER_BOX, PLAS_FILTER_BOX3
 MAX_CHANNELS = 64
 
 # Every symbol declared in include/plas.h, include/plas_stages.h and
@@ -69,6 +70,8 @@ class SortParams(ctypes.Structure):
         ("profile", ctypes.c_int32),
         ("reorders_per_sync", ctypes.c_int32),
         ("storage", ctypes.c_int32),
+        ("filter", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -313,12 +316,14 @@ class Context:
     def sort(self, features, side: int | None = None, seed: int = 0x5EED, layout: str = "cn", *,
              radius_decay: float = 0.95, inv_threshold: int = 10000, min_block: int = 16,
              start_radius: float = 0.0, max_reorders: int = 0, init_perm=None,
-             profile: bool = False, reorders_per_sync: int = 0, storage: str = "f32", out=None):
+             profile: bool = False, reorders_per_sync: int = 0, storage: str = "f32", out=None,
+             filter: str = "box"):
         """Sort device features ([d][n] for layout "cn", [n][d] for "nc",
         float32 or bfloat16, contiguous) onto a side x side grid, with the
-        working grids stored as float32 ("f32") or bfloat16 ("bf16"). Returns
-        (perm, stats): perm is an int32 device tensor in gather form, stats a
-        SortResult."""
+        working grids stored as float32 ("f32") or bfloat16 ("bf16") and the
+        target filtered by one box pass per axis ("box") or three ("box3",
+        Gaussian-like). Returns (perm, stats): perm is an int32 device tensor
+        in gather form, stats a SortResult."""
         import torch
         dtype = _feature_dtype(features)
         if layout == "cn":
@@ -336,7 +341,8 @@ class Context:
         _check_tensor(out, torch.int32)
         prm = _sort_params(seed=seed, radius_decay=radius_decay, inv_threshold=inv_threshold,
                            min_block=min_block, start_radius=start_radius, max_reorders=max_reorders,
-                           profile=profile, reorders_per_sync=reorders_per_sync, storage=storage)
+                           profile=profile, reorders_per_sync=reorders_per_sync, storage=storage,
+                           filter=filter)
         if init_perm is not None:
             _check_tensor(init_perm, torch.int32)
             prm.init_perm = init_perm.data_ptr()
@@ -674,7 +680,8 @@ class BatchResult:
 
 def _sort_params(seed: int = 0x5EED, radius_decay: float = 0.95, inv_threshold: int = 10000,
                  min_block: int = 16, start_radius: float = 0.0, max_reorders: int = 0,
-                 profile: bool = False, reorders_per_sync: int = 0, storage: str = "f32") -> SortParams:
+                 profile: bool = False, reorders_per_sync: int = 0, storage: str = "f32",
+                 filter: str = "box") -> SortParams:
     prm = SortParams()
     library().plas_sort_params_init(ctypes.byref(prm))
     prm.seed = seed & 0xFFFFFFFFFFFFFFFF
@@ -686,6 +693,7 @@ def _sort_params(seed: int = 0x5EED, radius_decay: float = 0.95, inv_threshold: 
     prm.profile = 1 if profile else 0
     prm.reorders_per_sync = reorders_per_sync
     prm.storage = STORAGES[storage]
+    prm.filter = FILTERS[filter]
     return prm
 
 

@@ -634,6 +634,8 @@ int32_t plas_sort_batch(plas_handle h, const plas_batch_item* items, int32_t cou
     return fail(h, PLAS_ERR_INVALID_ARGUMENT, "stats->struct_size does not match this library");
   plas_sort_params prm;
   int32_t st = check_params(h, params, &prm);
+  if (st == PLAS_OK && prm.filter != PLAS_FILTER_BOX)
+    st = fail(h, PLAS_ERR_INVALID_ARGUMENT, "batched sorts use the box filter");
   if (st != PLAS_OK) return st;
   plas_batch_config cfg;
   st = check_config(h, config, &cfg);
@@ -662,6 +664,8 @@ int32_t plas_autotune_batch(plas_handle h, const plas_batch_item* items, int32_t
   if (count >= kMaxSlots) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "too many sorts in one batch");
   plas_sort_params base;
   int32_t st = check_params(h, params, &base);
+  if (st == PLAS_OK && base.filter != PLAS_FILTER_BOX)
+    st = fail(h, PLAS_ERR_INVALID_ARGUMENT, "batched sorts use the box filter");
   if (st != PLAS_OK) return st;
   DeviceScope scope(h->device);
   if (!scope.ok()) return fail(h, PLAS_ERR_HIP, "hipSetDevice failed");
@@ -819,6 +823,8 @@ int32_t plas_server_create(plas_handle h, const plas_sort_params* params, const 
   if (s == nullptr) return fail(h, PLAS_ERR_OUT_OF_MEMORY, "server");
   s->h = h;
   int32_t st = check_params(h, params, &s->prm);
+  if (st == PLAS_OK && s->prm.filter != PLAS_FILTER_BOX)
+    st = fail(h, PLAS_ERR_INVALID_ARGUMENT, "served sorts use the box filter");
   if (st == PLAS_OK) st = check_config(h, config, &s->cfg);
   if (st != PLAS_OK) {
     delete s;

@@ -48,6 +48,7 @@ int32_t plas_sort_params_init(plas_sort_params* p) {
   p->profile = 0;
   p->reorders_per_sync = 0;
   p->storage = PLAS_STORAGE_F32;
+  p->filter = PLAS_FILTER_BOX;
   return PLAS_OK;
 }
 
@@ -193,6 +194,7 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
   plas_level_out* Td = as<plas_level_out>(h->trace);
   int32_t* table = as<int32_t>(h->table);
   const int chunk = prm.reorders_per_sync > 0 ? prm.reorders_per_sync : kDefaultReordersPerSync;
+  const int passes = prm.filter == PLAS_FILTER_BOX3 ? 3 : 1;  // box passes per axis
   const bool profile = prm.profile != 0;
   if (profile) {
     st = ensure_events(h, static_cast<size_t>(chunk) * 4);
@@ -204,16 +206,30 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
   int64_t slots = 0;  // reorder slots queued so far; slot i runs reorder i unless the sort has ended
   for (;;) {
     for (int i = 0; i < chunk; ++i) {
-      // The row pass first steps the controller from states[cur] to
+      // The first row pass steps the controller from states[cur] to
       // states[cur ^ 1] (and fills the grouping table); the rest of the
-      // reorder uses states[cur ^ 1].
+      // reorder uses states[cur ^ 1]. Each axis takes `passes` box passes
+      // (PLAS_FILTER_BOX3: three), through H and T in turn, the last
+      // column pass writing T: rows G -> H [-> T -> H], columns [H -> T ->
+      // H ->] H -> T.
       DevState* Sd = &states[cur ^ 1];
       const plas::StepArgs step{&states[cur], Sd, Ld, Td, table, max_cells};
       cur ^= 1;
       const bool timed = profile && i % kProfileEvery == 0;
       if (timed) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 0], h->stream));
-      PLAS_HIP(h, plas::launch_blur_pass(G, H, w, dp, storage, nullptr, 0, 0, as<float>(h->inv), h->stream, &step));
-      PLAS_HIP(h, plas::launch_blur_pass(H, T, w, dp, storage, Sd, 0, 1, as<float>(h->inv), h->stream));
+      void* bufs[2] = {H, T};
+      const void* src = G;
+      for (int p = 0; p < passes; ++p) {
+        void* dst = bufs[p & 1];
+        PLAS_HIP(h, plas::launch_blur_pass(src, dst, w, dp, storage, p == 0 ? nullptr : Sd, 0, 0,
+                                           as<float>(h->inv), h->stream, p == 0 ? &step : nullptr));
+        src = dst;
+      }
+      for (int p = 0; p < passes; ++p) {
+        void* dst = p == passes - 1 ? T : bufs[(passes + p) & 1];
+        PLAS_HIP(h, plas::launch_blur_pass(src, dst, w, dp, storage, Sd, 0, 1, as<float>(h->inv), h->stream));
+        src = dst;
+      }
       if (timed) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 1], h->stream));
       if (timed) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 2], h->stream));
       PLAS_HIP(h, plas::launch_assign(G, T, P, table, Sd, dp, storage, max_items, h->stream));
@@ -272,7 +288,7 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
       stats->trace_len = len;
     }
     stats->blur_ms = blur_ms;
-    stats->blur_launches = 2 * timed_reorders;
+    stats->blur_launches = 2 * passes * timed_reorders;
     stats->assign_ms = assign_ms;
     stats->assign_launches = timed_reorders;
     stats->total_ms =

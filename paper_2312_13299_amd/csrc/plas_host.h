@@ -316,6 +316,8 @@ inline int32_t check_params(plas_context* h, const plas_sort_params* params, pla
   if (prm->min_block < 1) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "min_block must be >= 1");
   if (prm->max_reorders < 0) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "max_reorders must be >= 0");
   if (!valid_storage(prm->storage)) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "unknown storage");
+  if (prm->filter != PLAS_FILTER_BOX && prm->filter != PLAS_FILTER_BOX3)
+    return fail(h, PLAS_ERR_INVALID_ARGUMENT, "unknown filter");
   return PLAS_OK;
 }
 

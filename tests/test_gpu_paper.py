@@ -3,6 +3,7 @@ measure against the oracle's and its closed forms, the random 512 x 512 x 3
 RGB sort against the oracle's stored result (permutation, counts, VAD), and
 sorts under other improvement thresholds (the threshold sweep) against the
 oracle directly."""
+import ctypes
 import hashlib
 import json
 import os
@@ -89,3 +90,66 @@ def test_threshold_sweep_matches_oracle(env, inv_threshold):
     assert want.status == 0
     assert res.reorders == want.reorders and res.energy_fixed == want.energy
     assert np.array_equal(perm.cpu().numpy(), want.perm)
+
+
+# The Gaussian-like target filter (three box passes per axis): whole sorts
+# against the oracle's, bit for bit, in both storages and layouts.
+@pytest.mark.parametrize("side,d,layout,storage,seed", [
+    (64, 3, "cn", "f32", 1), (48, 59, "cn", "f32", 2), (40, 59, "cn", "bf16", 3), (33, 14, "nc", "f32", 4),
+    (2, 3, "cn", "f32", 5), (17, 1, "cn", "f32", 6)])
+def test_box3_filter_sort_matches_oracle(env, side, d, layout, storage, seed):
+    torch, plas, ctx, ref = env
+    n = side * side
+    if d == 3:
+        F = synthetic.random_rgb_grid(side, seed) if layout == "cn" else None
+    else:
+        F = synthetic.gaussian_attributes(n, seed, layout)[:d] if layout == "cn" else \
+            synthetic.random_features(n, d, seed, layout, -2.0, 2.0)
+    if F is None:
+        F = synthetic.random_features(n, d, seed, layout, 0.0, 255.0)
+    F = np.ascontiguousarray(F)
+    perm, res = ctx.sort(torch.from_numpy(F).cuda(), side, seed, layout, storage=storage, filter="box3",
+                         profile=True)
+    want = ref.sort(F, side, seed, layout, storage_bf16=(storage == "bf16"), filter="box3")
+    assert want.status == 0
+    assert res.reorders == want.reorders and res.levels == want.levels
+    assert res.energy_fixed == want.energy and res.scale_shift == want.scale_shift
+    assert [(t["r"], t["reorders"], t["energy"], t["moved"]) for t in res.trace] == \
+           [(t["r"], t["reorders"], t["energy"], t["moved"]) for t in want.trace]
+    assert np.array_equal(perm.cpu().numpy(), want.perm)
+    # Six blur passes per timed reorder.
+    assert res.blur_launches == 6 * res.assign_launches
+
+
+def test_box3_filter_truncated_at_the_coarsest_levels(env):
+    """256 x 256, D = 59: the first 24 reorders (radius 127 and below, six
+    passes of windows up to 255 cells) against the oracle."""
+    torch, plas, ctx, ref = env
+    side = 256
+    F = synthetic.gaussian_attributes(side * side, 12)
+    perm, res = ctx.sort(torch.from_numpy(F).cuda(), side, 9, filter="box3", max_reorders=24)
+    want = ref.sort(F, side, 9, filter="box3", max_reorders=24)
+    assert res.reorders == want.reorders == 24 and res.energy_fixed == want.energy
+    assert np.array_equal(perm.cpu().numpy(), want.perm)
+
+
+def test_box3_filter_is_single_sort_only(env):
+    torch, plas, ctx, ref = env
+    f = torch.from_numpy(synthetic.gaussian_attributes(64, 1)).cuda()
+    L = plas.library()
+    prm = plas._sort_params(filter="box3")
+    items = (plas.BatchItem * 1)()
+    out = torch.empty(64, dtype=torch.int32, device="cuda")
+    items[0].features = f.data_ptr()
+    items[0].n, items[0].d, items[0].side = 64, 59, 8
+    items[0].perm_out = out.data_ptr()
+    cfg = plas._batch_config(False, 0, False, None)[0]
+    assert L.plas_sort_batch(ctx._h, items, 1, ctypes.byref(prm), ctypes.byref(cfg), None) == \
+        plas.ERR_INVALID_ARGUMENT
+    h = ctypes.c_void_p()
+    assert L.plas_server_create(ctx._h, ctypes.byref(prm), None, 1 << 30, ctypes.byref(h)) == \
+        plas.ERR_INVALID_ARGUMENT
+    bad = plas._sort_params()
+    bad.filter = 2
+    assert L.plas_sort(ctx._h, ctypes.c_void_p(f.data_ptr()), 64, 59, 8, plas.LAYOUT_CN, 0, ctypes.byref(bad),
+                       ctypes.c_void_p(out.data_ptr()), None) == plas.ERR_INVALID_ARGUMENT
