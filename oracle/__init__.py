@@ -33,6 +33,27 @@ def build(force: bool = True) -> str:
     return LIBRARY
 
 
+class State(ctypes.Structure):
+    """Where a sort stopped (plas_ref_state): resume it with this state and
+    the stopped sort's permutation as init_perm."""
+    _fields_ = [
+        ("k", ctypes.c_int64),
+        ("j", ctypes.c_uint64),
+        ("level", ctypes.c_int32),
+        ("levels_run", ctypes.c_int32),
+        ("dy", ctypes.c_int32),
+        ("dx", ctypes.c_int32),
+        ("has_prev", ctypes.c_int32),
+        ("just_shifted", ctypes.c_int32),
+        ("E_prev", ctypes.c_uint64),
+        ("E_last", ctypes.c_uint64),
+        ("level_reorders", ctypes.c_int64),
+        ("level_moved", ctypes.c_uint64),
+        ("done", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
 class _Params(ctypes.Structure):
     _fields_ = [
         ("seed", ctypes.c_uint64),
@@ -44,6 +65,7 @@ class _Params(ctypes.Structure):
         ("init_perm", ctypes.c_void_p),
         ("storage_bf16", ctypes.c_int32),
         ("filter", ctypes.c_int32),
+        ("resume", ctypes.POINTER(State)),
     ]
 
 
@@ -75,6 +97,7 @@ class _Result(ctypes.Structure):
         ("trace_len", ctypes.c_int32),
         ("reorder_energy", ctypes.POINTER(ctypes.c_uint64)),
         ("reorder_energy_cap", ctypes.c_int64),
+        ("state", ctypes.POINTER(State)),
     ]
 
 
@@ -301,18 +324,23 @@ class SortResult:
     energy_mean: float = 0.0
     trace: list = field(default_factory=list)
     reorder_energy: np.ndarray | None = None
+    state: State | None = None  # where the sort stopped
 
 
 def sort(F: np.ndarray, side: int, seed: int, layout: str = "cn", *, radius_decay: float = 0.95,
          inv_threshold: int = 10000, min_block: int = 16, start_radius: float = 0.0,
          max_reorders: int = 0, init_perm: np.ndarray | None = None,
-         energy_cap: int = 0, storage_bf16: bool = False, filter: str = "box") -> SortResult:
+         energy_cap: int = 0, storage_bf16: bool = False, filter: str = "box",
+         resume: State | None = None) -> SortResult:
+    """The whole sort (or its continuation from `resume`, with init_perm the
+    stopped sort's permutation). The result's `state` says where it stopped."""
     F = _f32(F)
     n, d = _nd(F, layout)
     ip = None if init_perm is None else np.ascontiguousarray(init_perm, dtype=np.int32)
     prm = _Params(seed & 0xFFFFFFFFFFFFFFFF, radius_decay, inv_threshold, min_block,
                   start_radius, max_reorders, None if ip is None else ip.ctypes.data,
-                  1 if storage_bf16 else 0, FILTERS[filter])
+                  1 if storage_bf16 else 0, FILTERS[filter],
+                  None if resume is None else ctypes.pointer(resume))
     cap = 4096
     trace = (_Level * cap)()
     energies = np.zeros(max(energy_cap, 1), dtype=np.uint64)
@@ -321,12 +349,15 @@ def sort(F: np.ndarray, side: int, seed: int, layout: str = "cn", *, radius_deca
     res.trace_cap = cap
     res.reorder_energy = energies.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)) if energy_cap else None
     res.reorder_energy_cap = energy_cap
+    state = State()
+    res.state = ctypes.pointer(state)
     perm = np.empty(n, dtype=np.int32)
     st = lib().plas_ref_sort(_ptr(F), n, d, side, LAYOUTS[layout], ctypes.byref(prm), _ptr(perm),
                              ctypes.byref(res))
     out = SortResult(status=int(st), perm=perm)
     if st != OK:
         return out
+    out.state = state
     out.reorders = res.reorders
     out.levels = res.levels
     out.scale_shift = res.scale_shift

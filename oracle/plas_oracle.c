@@ -664,6 +664,10 @@ int32_t plas_ref_sort(const float* F, int64_t n, int32_t d, int32_t side, int32_
     int32_t st = plas_ref_scale_shift(F, n, d, layout, &s, NULL);
     if (st == PLAS_REF_OK && prm->init_perm && !is_bijection(prm->init_perm, N))
         st = PLAS_REF_INVALID;
+    if (st == PLAS_REF_OK && prm->resume &&
+        (prm->init_perm == NULL || prm->resume->k < 0 || prm->resume->level < 0 ||
+         prm->resume->levels_run < 0 || prm->resume->levels_run > prm->resume->level))
+        st = PLAS_REF_INVALID;
     if (st != PLAS_REF_OK) {
         free(rounded);
         return st;
@@ -696,9 +700,25 @@ int32_t plas_ref_sort(const float* F, int64_t n, int32_t d, int32_t side, int32_
     int32_t levels = 0;
     uint64_t E_last = 0;
     int stop = 0;
+    int32_t level_index = 0;
     double phi = prm->start_radius > 0.0 ? prm->start_radius : (double)w / 2.0 - 1.0;
     if (phi < 1.0)
         phi = 1.0;
+    /* Resume: the counters, and phi after the levels already entered. */
+    const plas_ref_state* R = prm->resume;
+    int resume_in_level = 0;
+    if (R) {
+        k = R->k;
+        j = R->j;
+        levels = R->levels_run;
+        E_last = R->E_last;
+        for (level_index = 0; level_index < R->level; level_index++)
+            phi = phi * prm->radius_decay;
+        resume_in_level = !R->done;
+        if (R->done)
+            phi = 0.0;
+    }
+    plas_ref_state at = {0};
     while (phi >= 1.0 && !stop) {
         int32_t r = (int32_t)floor(phi);
         int32_t beta = r + 1;
@@ -707,15 +727,36 @@ int32_t plas_ref_sort(const float* F, int64_t n, int32_t d, int32_t side, int32_
         if (beta > w)
             beta = w;
         int32_t dy, dx;
-        plas_ref_shift(prm->seed, j, w, &dy, &dx);
-        j++;
         int has_prev = 0, just_shifted = 0;
         uint64_t E_prev = 0;
         int64_t level_reorders = 0;
         uint64_t level_moved = 0;
+        if (resume_in_level) {
+            /* Inside a level: its shift and stall state as they were. */
+            dy = R->dy;
+            dx = R->dx;
+            has_prev = R->has_prev != 0;
+            just_shifted = R->just_shifted != 0;
+            E_prev = R->E_prev;
+            level_reorders = R->level_reorders;
+            level_moved = R->level_moved;
+            resume_in_level = 0;
+        } else {
+            plas_ref_shift(prm->seed, j, w, &dy, &dx);
+            j++;
+        }
         for (;;) {
             if (prm->max_reorders > 0 && k >= prm->max_reorders) {
                 stop = 1;
+                at.level = level_index;
+                at.levels_run = levels;
+                at.dy = dy;
+                at.dx = dx;
+                at.has_prev = has_prev;
+                at.just_shifted = just_shifted;
+                at.E_prev = E_prev;
+                at.level_reorders = level_reorders;
+                at.level_moved = level_moved;
                 break;
             }
             plas_ref_blur_filter(G, T, w, d, r, bf16, prm->filter);
@@ -755,8 +796,21 @@ int32_t plas_ref_sort(const float* F, int64_t n, int32_t d, int32_t side, int32_
             }
             levels++;
         }
-        phi = phi * prm->radius_decay;
+        if (!stop) {
+            phi = phi * prm->radius_decay;
+            level_index++;
+        }
     }
+    if (!stop) {
+        at.level = level_index;
+        at.levels_run = levels;
+        at.done = 1;
+    }
+    at.k = k;
+    at.j = j;
+    at.E_last = E_last;
+    if (res && res->state)
+        *res->state = at;
     memcpy(perm_out, P, sizeof(int32_t) * (size_t)N);
     if (res) {
         res->reorders = k;

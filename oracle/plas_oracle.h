@@ -36,6 +36,26 @@ extern "C" {
 #define PLAS_REF_LAYOUT_CN 0
 #define PLAS_REF_LAYOUT_NC 1
 
+/* Where a sort stopped (at max_reorders, before the next reorder), so that
+ * a later call can resume it: with this state and the stopped call's
+ * permutation as init_perm, the resumed sort ends with the permutation,
+ * reorder count, energy and trace of the uninterrupted one. */
+typedef struct {
+    int64_t k;               /* reorders done */
+    uint64_t j;              /* shift draws done */
+    int32_t level;           /* schedule levels entered (phi = phi0 * decay^level) */
+    int32_t levels_run;      /* levels finished that ran a reorder (the current one excluded) */
+    int32_t dy, dx;          /* the current level's block shift */
+    int32_t has_prev;        /* the current level has an energy to compare with */
+    int32_t just_shifted;    /* the last reorder stalled and a new shift was drawn */
+    uint64_t E_prev;         /* the energy compared with */
+    uint64_t E_last;         /* energy after the last reorder */
+    int64_t level_reorders;  /* reorders of the current level so far */
+    uint64_t level_moved;    /* cells moved in the current level so far */
+    int32_t done;            /* nonzero: the schedule has ended */
+    int32_t reserved;
+} plas_ref_state;
+
 typedef struct {
     uint64_t seed;
     double radius_decay;      /* 0.95 (Sec. 3.1) */
@@ -46,6 +66,8 @@ typedef struct {
     const int32_t* init_perm; /* NULL: random start (Sec. 3.1) */
     int32_t storage_bf16;     /* nonzero: features and blurred grids held in bfloat16 */
     int32_t filter;           /* PLAS_REF_FILTER_BOX (0) or PLAS_REF_FILTER_BOX3 (1) */
+    const plas_ref_state* resume; /* NULL: a new sort; else continue from this state, init_perm
+                                     holding the stopped sort's permutation */
 } plas_ref_params;
 
 /* The low-pass filter of the target. BOX: one box pass per axis. BOX3: the
@@ -74,6 +96,7 @@ typedef struct {
     int32_t trace_len;
     uint64_t* reorder_energy;   /* caller-owned, may be NULL: E after each reorder */
     int64_t reorder_energy_cap;
+    plas_ref_state* state;      /* caller-owned, may be NULL: where the sort stopped */
 } plas_ref_result;
 
 /* Philox4x64-10 block: out = Philox(ctr, key). */
