@@ -77,6 +77,32 @@ extern "C" {
 typedef struct plas_context* plas_handle;
 
 /*
+ * Where a sort stopped: after params->max_reorders reorders, or at the end of
+ * its schedule (done). Passed back as params->resume, with the stopped sort's
+ * permutation as params->init_perm and the same features, side, seed and
+ * other parameters, it continues the sort, which then ends with the
+ * permutation, reorder count, energy and per-level statistics of the sort run
+ * without a stop (its trace holds only the levels run after the resume). The
+ * fields are the state of the Sec. 3.1 controller (radius level, block shift
+ * and stall test); a caller stores and returns them unchanged.
+ */
+typedef struct {
+    uint32_t struct_size;    /* sizeof(plas_sort_checkpoint) */
+    int32_t done;            /* nonzero: the schedule has ended, nothing is left to run */
+    int64_t reorders;        /* reorders run so far */
+    uint64_t shift_draws;    /* block shifts drawn so far */
+    int32_t level;           /* radius level the next reorder belongs to */
+    int32_t levels_done;     /* levels before it that ran at least one reorder */
+    int32_t dy, dx;          /* that level's current block shift */
+    int32_t has_prev;        /* the level has an energy to compare the next one with */
+    int32_t just_shifted;    /* the last reorder stalled and the shift was redrawn */
+    uint64_t energy_prev;    /* the energy compared with */
+    uint64_t energy_last;    /* integer energy after the last reorder */
+    int64_t level_reorders;  /* reorders of the current level so far */
+    uint64_t level_moved;    /* cells moved in the current level so far */
+} plas_sort_checkpoint;
+
+/*
  * Sort parameters. Defaults (plas_sort_params_init) follow Sec. 3.1:
  * radius decay 0.95, a 0.01 % improvement threshold, blocks of at least 16,
  * start radius side/2 - 1.
@@ -95,6 +121,7 @@ typedef struct {
     int32_t storage;         /* PLAS_STORAGE_F32 (default) or PLAS_STORAGE_BF16 */
     int32_t filter;          /* PLAS_FILTER_BOX (default) or PLAS_FILTER_BOX3 */
     int32_t reserved;        /* 0 */
+    const plas_sort_checkpoint* resume; /* host, or NULL for a new sort; needs init_perm (plas_sort only) */
 } plas_sort_params;
 
 /* One radius level of a finished sort. */
@@ -126,6 +153,7 @@ typedef struct {
     double assign_ms;       /* assignment kernel */
     int64_t assign_launches;
     double total_ms;        /* wall time of the whole call */
+    plas_sort_checkpoint* checkpoint; /* caller-owned host struct, or NULL: where the sort stopped */
 } plas_sort_stats;
 
 int32_t plas_get_abi_version(void);

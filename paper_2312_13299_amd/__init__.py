@@ -57,6 +57,27 @@ class PlasError(RuntimeError):
         self.status = status
 
 
+class Checkpoint(ctypes.Structure):
+    """plas_sort_checkpoint: where a sort stopped. Pass it back as
+    Context.sort(..., resume=cp, init_perm=perm) to continue."""
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("done", ctypes.c_int32),
+        ("reorders", ctypes.c_int64),
+        ("shift_draws", ctypes.c_uint64),
+        ("level", ctypes.c_int32),
+        ("levels_done", ctypes.c_int32),
+        ("dy", ctypes.c_int32),
+        ("dx", ctypes.c_int32),
+        ("has_prev", ctypes.c_int32),
+        ("just_shifted", ctypes.c_int32),
+        ("energy_prev", ctypes.c_uint64),
+        ("energy_last", ctypes.c_uint64),
+        ("level_reorders", ctypes.c_int64),
+        ("level_moved", ctypes.c_uint64),
+    ]
+
+
 class SortParams(ctypes.Structure):
     _fields_ = [
         ("struct_size", ctypes.c_uint32),
@@ -72,6 +93,7 @@ class SortParams(ctypes.Structure):
         ("storage", ctypes.c_int32),
         ("filter", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("resume", ctypes.POINTER(Checkpoint)),
     ]
 
 
@@ -103,6 +125,7 @@ class SortStats(ctypes.Structure):
         ("assign_ms", ctypes.c_double),
         ("assign_launches", ctypes.c_int64),
         ("total_ms", ctypes.c_double),
+        ("checkpoint", ctypes.POINTER(Checkpoint)),
     ]
 
 
@@ -317,13 +340,14 @@ class Context:
              radius_decay: float = 0.95, inv_threshold: int = 10000, min_block: int = 16,
              start_radius: float = 0.0, max_reorders: int = 0, init_perm=None,
              profile: bool = False, reorders_per_sync: int = 0, storage: str = "f32", out=None,
-             filter: str = "box"):
+             filter: str = "box", resume: Checkpoint | None = None):
         """Sort device features ([d][n] for layout "cn", [n][d] for "nc",
         float32 or bfloat16, contiguous) onto a side x side grid, with the
         working grids stored as float32 ("f32") or bfloat16 ("bf16") and the
         target filtered by one box pass per axis ("box") or three ("box3",
         Gaussian-like). Returns (perm, stats): perm is an int32 device tensor
-        in gather form, stats a SortResult."""
+        in gather form, stats a SortResult whose checkpoint says where the
+        sort stopped; pass it as resume, with perm as init_perm, to go on."""
         import torch
         dtype = _feature_dtype(features)
         if layout == "cn":
@@ -346,6 +370,8 @@ class Context:
         if init_perm is not None:
             _check_tensor(init_perm, torch.int32)
             prm.init_perm = init_perm.data_ptr()
+        if resume is not None:
+            prm.resume = ctypes.pointer(resume)
         stats, trace = _new_stats()
         self._bind_stream()
         st = library().plas_sort(self._h, ctypes.c_void_p(features.data_ptr()), n, d, side, lay,
@@ -566,6 +592,7 @@ class SortResult:
     assign_ms: float = 0.0
     assign_launches: int = 0
     total_ms: float = 0.0
+    checkpoint: Checkpoint | None = None  # where the sort stopped
 
 
 def _batch_config(graph: bool, reorders_per_sync: int, profile: bool, tune):
@@ -706,6 +733,8 @@ def _new_stats():
     stats.struct_size = ctypes.sizeof(SortStats)
     stats.trace = ctypes.cast(trace, ctypes.POINTER(LevelStat))
     stats.trace_cap = TRACE_CAP
+    stats._checkpoint = Checkpoint()  # kept alive with the stats
+    stats.checkpoint = ctypes.pointer(stats._checkpoint)
     return stats, trace
 
 
@@ -718,7 +747,7 @@ def _result(stats: SortStats, trace) -> SortResult:
                for t in trace[: stats.trace_len]],
         blur_ms=stats.blur_ms, blur_launches=stats.blur_launches,
         assign_ms=stats.assign_ms, assign_launches=stats.assign_launches,
-        total_ms=stats.total_ms)
+        total_ms=stats.total_ms, checkpoint=Checkpoint.from_buffer_copy(stats._checkpoint))
 
 
 def _feature_dtype(t) -> int:

@@ -435,6 +435,8 @@ class BatchRun {
       stats->assign_ms = 0.0;
       stats->assign_launches = 0;
       stats->total_ms = s.done_ms - s.submit_ms;
+      if (stats->checkpoint != nullptr)
+        fill_checkpoint(*S, static_cast<int32_t>(s.levels.size()), stats->checkpoint);
     }
     s.running = false;
     release(s.mem);
@@ -636,6 +638,8 @@ int32_t plas_sort_batch(plas_handle h, const plas_batch_item* items, int32_t cou
   int32_t st = check_params(h, params, &prm);
   if (st == PLAS_OK && prm.filter != PLAS_FILTER_BOX)
     st = fail(h, PLAS_ERR_INVALID_ARGUMENT, "batched sorts use the box filter");
+  if (st == PLAS_OK && prm.resume != nullptr)
+    st = fail(h, PLAS_ERR_INVALID_ARGUMENT, "batched sorts start from their items");
   if (st != PLAS_OK) return st;
   plas_batch_config cfg;
   st = check_config(h, config, &cfg);
@@ -666,6 +670,8 @@ int32_t plas_autotune_batch(plas_handle h, const plas_batch_item* items, int32_t
   int32_t st = check_params(h, params, &base);
   if (st == PLAS_OK && base.filter != PLAS_FILTER_BOX)
     st = fail(h, PLAS_ERR_INVALID_ARGUMENT, "batched sorts use the box filter");
+  if (st == PLAS_OK && base.resume != nullptr)
+    st = fail(h, PLAS_ERR_INVALID_ARGUMENT, "batched sorts start from their items");
   if (st != PLAS_OK) return st;
   DeviceScope scope(h->device);
   if (!scope.ok()) return fail(h, PLAS_ERR_HIP, "hipSetDevice failed");
@@ -825,6 +831,8 @@ int32_t plas_server_create(plas_handle h, const plas_sort_params* params, const 
   int32_t st = check_params(h, params, &s->prm);
   if (st == PLAS_OK && s->prm.filter != PLAS_FILTER_BOX)
     st = fail(h, PLAS_ERR_INVALID_ARGUMENT, "served sorts use the box filter");
+  if (st == PLAS_OK && s->prm.resume != nullptr)
+    st = fail(h, PLAS_ERR_INVALID_ARGUMENT, "served sorts start from their jobs");
   if (st == PLAS_OK) st = check_config(h, config, &s->cfg);
   if (st != PLAS_OK) {
     delete s;

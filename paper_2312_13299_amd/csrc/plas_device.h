@@ -51,7 +51,7 @@ struct DevState {
   int32_t levels_run;
   uint32_t inv_threshold;
   int32_t pending;  // a reorder has run whose result the controller has not seen
-  int32_t pad;
+  int32_t ended;    // the schedule ended (done for another reason: max_reorders)
   int64_t k;  // reorders done
   int64_t max_reorders;
   int64_t level_reorders;

@@ -184,6 +184,10 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
   // First reorder's state.
   DevState* S = h->state_host;
   init_sort_state(S, w, s, levels, prm, prm.seed);
+  if (prm.resume != nullptr) {
+    st = apply_checkpoint(h, S, *prm.resume, levels);
+    if (st != PLAS_OK) return st;
+  }
   // State buffers: each reorder's step launch reads states[cur] and writes
   // states[cur ^ 1], which the reorder's kernels then use.
   DevState* states = as<DevState>(h->state);
@@ -293,6 +297,7 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
     stats->assign_launches = timed_reorders;
     stats->total_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (stats->checkpoint != nullptr) fill_checkpoint(*S, static_cast<int32_t>(levels.size()), stats->checkpoint);
   }
   return PLAS_OK;
 }

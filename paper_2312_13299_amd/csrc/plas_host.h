@@ -302,6 +302,58 @@ inline void init_sort_state(DevState* S, int32_t w, int32_t s, const std::vector
   for (int i = 0; i < 4; ++i) S->keys[i] = keys.v[i];
 }
 
+// The checkpoint of a sort's final state S (schedule of nlevels levels). The
+// device counts a level in levels_run from its first reorder; the checkpoint
+// counts the levels before the current one.
+inline void fill_checkpoint(const DevState& S, int32_t nlevels, plas_sort_checkpoint* ck) {
+  std::memset(ck, 0, sizeof(*ck));
+  ck->struct_size = sizeof(plas_sort_checkpoint);
+  ck->done = S.ended;
+  ck->reorders = S.k;
+  ck->shift_draws = S.j;
+  ck->level = S.ended ? nlevels : S.level;
+  ck->levels_done = S.levels_run - (!S.ended && S.level_reorders > 0 ? 1 : 0);
+  ck->dy = S.dy;
+  ck->dx = S.dx;
+  ck->has_prev = S.has_prev;
+  ck->just_shifted = S.just_shifted;
+  ck->energy_prev = S.energy_prev;
+  ck->energy_last = S.energy_last;
+  ck->level_reorders = S.level_reorders;
+  ck->level_moved = S.level_moved;
+}
+
+// Set up S (made by init_sort_state) to continue from a checkpoint.
+inline int32_t apply_checkpoint(plas_context* h, DevState* S, const plas_sort_checkpoint& ck,
+                                const std::vector<LevelInfo>& levels) {
+  const int32_t nlevels = static_cast<int32_t>(levels.size());
+  if (ck.struct_size != sizeof(plas_sort_checkpoint))
+    return fail(h, PLAS_ERR_INVALID_ARGUMENT, "resume->struct_size does not match this library");
+  if (ck.reorders < 0 || ck.levels_done < 0 || ck.level_reorders < 0 || ck.level < 0 ||
+      (ck.done ? ck.level != nlevels : ck.level >= nlevels) || ck.levels_done > ck.level ||
+      ck.dy < 0 || ck.dy >= S->w || ck.dx < 0 || ck.dx >= S->w)
+    return fail(h, PLAS_ERR_INVALID_ARGUMENT, "resume does not fit this sort's schedule");
+  if (!ck.done) fill_state_for_level(S, levels[ck.level]);
+  S->level = ck.done ? nlevels - 1 : ck.level;
+  S->k = ck.reorders;
+  S->j = ck.shift_draws;
+  S->levels_run = ck.levels_done + (!ck.done && ck.level_reorders > 0 ? 1 : 0);
+  S->dy = ck.dy;
+  S->dx = ck.dx;
+  S->has_prev = ck.has_prev != 0;
+  S->just_shifted = ck.just_shifted != 0;
+  S->energy_prev = ck.energy_prev;
+  S->energy_last = ck.energy_last;
+  S->level_reorders = ck.level_reorders;
+  S->level_moved = ck.level_moved;
+  S->pending = 0;
+  S->ended = ck.done != 0;
+  S->done = S->ended || (S->max_reorders > 0 && S->k >= S->max_reorders);
+  const plas::Words4 keys = plas::draw(S->seed, plas::kDrawGrouping, static_cast<uint64_t>(S->k));
+  for (int i = 0; i < 4; ++i) S->keys[i] = keys.v[i];
+  return PLAS_OK;
+}
+
 // Shared checks of the sort parameters (plas_sort and plas_sort_batch).
 inline int32_t check_params(plas_context* h, const plas_sort_params* params, plas_sort_params* prm) {
   plas_sort_params_init(prm);
@@ -318,6 +370,8 @@ inline int32_t check_params(plas_context* h, const plas_sort_params* params, pla
   if (!valid_storage(prm->storage)) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "unknown storage");
   if (prm->filter != PLAS_FILTER_BOX && prm->filter != PLAS_FILTER_BOX3)
     return fail(h, PLAS_ERR_INVALID_ARGUMENT, "unknown filter");
+  if (prm->resume != nullptr && prm->init_perm == nullptr)
+    return fail(h, PLAS_ERR_INVALID_ARGUMENT, "resume needs init_perm (the stopped sort's permutation)");
   return PLAS_OK;
 }
 

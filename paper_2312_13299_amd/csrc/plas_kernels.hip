@@ -1349,6 +1349,7 @@ __device__ void control_step(DevState& st, const LevelInfo* __restrict__ levels,
     const int next = L + 1;
     if (next >= st.nlevels) {
       st.done = 1;
+      st.ended = 1;
     } else {
       const LevelInfo lv = levels[next];
       st.level = next;

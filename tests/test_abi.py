@@ -61,7 +61,9 @@ def test_params_defaults_follow_the_paper(plas):
 
 def test_struct_layouts(plas):
     assert ctypes.sizeof(plas.LevelStat) == 40
-    assert ctypes.sizeof(plas.SortParams) == 72
+    assert ctypes.sizeof(plas.SortParams) == 80
+    assert ctypes.sizeof(plas.SortStats) == 104
+    assert ctypes.sizeof(plas.Checkpoint) == 80
 
 
 def test_library_philox_matches_numpy(plas):
