@@ -120,3 +120,17 @@ def test_resume_errors_and_finished_sorts(env):
     cfg = plas._batch_config(False, 0, False, None)[0]
     assert plas.library().plas_sort_batch(ctx._h, items, 1, ctypes.byref(prm), ctypes.byref(cfg), None) == \
         plas.ERR_INVALID_ARGUMENT
+
+
+def test_batch_checkpoints_equal_single_sort_checkpoints(env):
+    torch, plas, ctx, ref = env
+    sides, seeds = [24, 33, 40], [11, 12, 13]
+    feats = [torch.from_numpy(synthetic.gaussian_attributes(s * s, s)).cuda() for s in sides]
+    for max_reorders in (7, 0):
+        perms, results, _ = ctx.sort_batch(feats, sides=sides, seeds=seeds, max_reorders=max_reorders)
+        for f, s, seed, perm, res in zip(feats, sides, seeds, perms, results):
+            p1, r1 = ctx.sort(f, s, seed, max_reorders=max_reorders)
+            assert torch.equal(p1, perm)
+            a, b = r1.checkpoint, res.checkpoint
+            assert bytes(a) == bytes(b), (s, max_reorders)
+            assert a.done == (max_reorders == 0)
