@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define PLAS_ABI_VERSION 1
+#define PLAS_ABI_VERSION 2
 
 /* Status codes. */
 #define PLAS_OK 0

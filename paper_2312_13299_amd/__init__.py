@@ -35,6 +35,7 @@ STORAGE_F32 = 0
 STORAGE_BF16 = 1
 STORAGES = {"f32": STORAGE_F32, "bf16": STORAGE_BF16}
 FILTERS = {"box": 0, "box3": 1}  # PLAS_FILTER_BOX, PLAS_FILTER_BOX3
+ABI_VERSION = 2  # PLAS_ABI_VERSION of include/plas.h
 MAX_CHANNELS = 64
 
 # Every symbol declared in include/plas.h, include/plas_stages.h and
@@ -238,8 +239,8 @@ def library() -> ctypes.CDLL:
         fn = getattr(L, name)
         fn.restype = res
         fn.argtypes = args
-    if L.plas_get_abi_version() != 1:
-        raise ImportError("libplas.so ABI version mismatch")
+    if L.plas_get_abi_version() != ABI_VERSION:
+        raise ImportError(f"libplas.so ABI version {L.plas_get_abi_version()}, this binding needs {ABI_VERSION}")
     _lib = L
     return L
 

@@ -45,7 +45,7 @@ def test_every_declared_symbol_is_exported(plas):
 
 
 def test_abi_version_and_status_strings(plas):
-    assert plas.library().plas_get_abi_version() == 1
+    assert plas.library().plas_get_abi_version() == 2
     for st in (0, -1, -2, -3, -4, -5):
         assert plas.status_string(st) not in ("", "unknown status")
     assert plas.status_string(-99) == "unknown status"
