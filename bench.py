@@ -350,7 +350,8 @@ def main() -> int:
     ap.add_argument("--jobs", type=int, default=16, help="serve: jobs per trace")
     ap.add_argument("--no-autotune", action="store_true", help="batch: use the default launch shapes")
     ap.add_argument("--side", type=int, default=0, help="grid side (default: the workload's)")
-    ap.add_argument("--cpu-sample-reorders", type=int, default=40)
+    ap.add_argument("--cpu-sample-reorders", type=int, default=120,
+                    help="reorders of the CPU oracle sample (about 10-15 s on 16 host cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-compare", action="store_true",
                     help="precision workload: skip the float32 sort of the same input")
