@@ -67,7 +67,7 @@ extern "C" {
  * PLAS_FILTER_BOX3: the same box pass three times per axis, rows then
  * columns: a Gaussian-like kernel of variance r(r+1) per axis and support
  * 3r (repeated uniform filters, Wells 1986); three times the blur work.
- * plas_sort only; batches, servers and the energy query use the box. */
+ * Sorts, batches and servers take either; the energy query uses the box. */
 #define PLAS_FILTER_BOX 0
 #define PLAS_FILTER_BOX3 1
 

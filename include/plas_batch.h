@@ -94,11 +94,10 @@ int32_t plas_batch_config_init(plas_batch_config* c);
  * decay, threshold, min_block, start_radius, max_reorders (its seed,
  * init_perm, storage, profile and reorders_per_sync fields are ignored: seed,
  * start arrangement and storage come from each item, the rest from config).
- * Batched sorts use the box filter and start from their items: a params
- * filter other than PLAS_FILTER_BOX, or a params resume, returns
- * PLAS_ERR_INVALID_ARGUMENT (here, in plas_autotune_batch and in
- * plas_server_create). A stopped sort's stats->checkpoint is filled as in
- * plas_sort. params and config may be NULL for the defaults; stats may be
+ * params->filter applies to every sort of the batch. Batched sorts start
+ * from their items: a params resume returns PLAS_ERR_INVALID_ARGUMENT (here,
+ * in plas_autotune_batch and in plas_server_create). A stopped sort's
+ * stats->checkpoint is filled as in plas_sort. params and config may be NULL for the defaults; stats may be
  * NULL.
  * Items must not share perm_out buffers. The device memory of a sort
  * (3 grids plus about 8 bytes per cell) is held from its start until it

@@ -429,7 +429,8 @@ class Context:
     def sort_batch(self, features_list, sides=None, seeds=0x5EED, layouts="cn", storages="f32",
                    init_perms=None, *, graph: bool = False, tune=None, reorders_per_sync: int = 0,
                    profile: bool = False, radius_decay: float = 0.95, inv_threshold: int = 10000,
-                   min_block: int = 16, start_radius: float = 0.0, max_reorders: int = 0, out=None):
+                   min_block: int = 16, start_radius: float = 0.0, max_reorders: int = 0, out=None,
+                   filter: str = "box"):
         """Sort several grids together (plas_sort_batch). Per-sort arguments
         (sides, seeds, layouts, storages, init_perms, out) take one value for
         all or a list. tune: list of dicts with side_lo, side_hi,
@@ -438,7 +439,7 @@ class Context:
         count = len(features_list)
         items, keep = self._batch_items(features_list, sides, seeds, layouts, storages, init_perms, out)
         prm = _sort_params(radius_decay=radius_decay, inv_threshold=inv_threshold, min_block=min_block,
-                           start_radius=start_radius, max_reorders=max_reorders)
+                           start_radius=start_radius, max_reorders=max_reorders, filter=filter)
         cfg, table = _batch_config(graph, reorders_per_sync, profile, tune)
         bstats = BatchStats()
         bstats.struct_size = ctypes.sizeof(BatchStats)
@@ -631,11 +632,11 @@ class Server:
 
     def __init__(self, ctx: "Context", memory_budget: int, *, graph: bool = False, reorders_per_sync: int = 0,
                  tune=None, radius_decay: float = 0.95, inv_threshold: int = 10000, min_block: int = 16,
-                 start_radius: float = 0.0, max_reorders: int = 0):
+                 start_radius: float = 0.0, max_reorders: int = 0, filter: str = "box"):
         self.ctx = ctx
         self._h = ctypes.c_void_p()
         prm = _sort_params(radius_decay=radius_decay, inv_threshold=inv_threshold, min_block=min_block,
-                           start_radius=start_radius, max_reorders=max_reorders)
+                           start_radius=start_radius, max_reorders=max_reorders, filter=filter)
         cfg, self._table = _batch_config(graph, reorders_per_sync, False, tune)
         ctx._bind_stream()
         st = library().plas_server_create(ctx._h, ctypes.byref(prm), ctypes.byref(cfg), int(memory_budget),

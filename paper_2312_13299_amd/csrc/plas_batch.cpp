@@ -185,6 +185,20 @@ class BatchRun {
       : h_(h), b_(b), prm_(prm), cfg_(cfg), t0_(t0) {
     chunk_ = cfg.reorders_per_sync > 0 ? cfg.reorders_per_sync : plas_host::kDefaultReordersPerSync;
     graph_ = cfg.graph != 0 && cfg.profile == 0;
+    // Blur passes per axis (PLAS_FILTER_BOX3: three), through H and T in
+    // turn, the last column pass writing T (as plas_sort does).
+    const int passes = prm.filter == PLAS_FILTER_BOX3 ? 3 : 1;
+    int src = 0;  // G
+    for (int p = 0; p < passes; ++p) {
+      const int dst = 1 + (p & 1);
+      routes_.push_back(plas::blur_route(0, src, dst, p == 0));
+      src = dst;
+    }
+    for (int p = 0; p < passes; ++p) {
+      const int dst = p == passes - 1 ? 2 : 1 + ((passes + p) & 1);
+      routes_.push_back(plas::blur_route(1, src, dst, 0));
+      src = dst;
+    }
     if (graph_ && (chunk_ & 1)) ++chunk_;  // a replay must end on the parity it started on
   }
   ~BatchRun() {
@@ -504,7 +518,7 @@ class BatchRun {
     PLAS_HIP(h_, reserve_pinned(&b_->status_host, &b_->status_host_bytes, status_bytes));
     // Reorder launches: step, blur rows (each blur launch), blur columns, assignments.
     int per_reorder = 0;
-    for (const Launch& L : launches_) per_reorder += L.kind == kBlur ? 2 : 1;
+    for (const Launch& L : launches_) per_reorder += L.kind == kBlur ? static_cast<int>(routes_.size()) : 1;
     launches_per_chunk_ = static_cast<int64_t>(per_reorder) * chunk_;
     if (cfg_.profile) {
       while (b_->events.size() < static_cast<size_t>(4 * chunk_)) {
@@ -529,11 +543,11 @@ class BatchRun {
       if (timed) PLAS_HIP(h_, hipEventRecord(b_->events[4 * i + 0], stream));
       cur_ ^= 1;
       if (timed) PLAS_HIP(h_, hipEventRecord(b_->events[4 * i + 1], stream));
-      for (int vertical = 0; vertical < 2; ++vertical)
+      for (const int route : routes_)
         for (const Launch& L : launches_)
           if (L.kind == kBlur)
             PLAS_HIP(h_, plas::launch_blur_batch(grids, map_of(L), L.blocks, L.dp, L.storage, L.wpb == 0 ? 4 : L.wpb,
-                                                 cur_, vertical, stream));
+                                                 cur_, route, stream));
       if (timed) PLAS_HIP(h_, hipEventRecord(b_->events[4 * i + 2], stream));
       for (const Launch& L : launches_)
         if (L.kind == kAssign)
@@ -549,6 +563,7 @@ class BatchRun {
   plas_batch_config cfg_;
   std::chrono::steady_clock::time_point t0_;
   int chunk_ = 32;
+  std::vector<int> routes_;  // blur passes of a reorder, in order
   bool graph_ = false;
   bool dirty_ = true;
   int cur_ = 0;  // state read by the next chunk's first step
@@ -636,8 +651,6 @@ int32_t plas_sort_batch(plas_handle h, const plas_batch_item* items, int32_t cou
     return fail(h, PLAS_ERR_INVALID_ARGUMENT, "stats->struct_size does not match this library");
   plas_sort_params prm;
   int32_t st = check_params(h, params, &prm);
-  if (st == PLAS_OK && prm.filter != PLAS_FILTER_BOX)
-    st = fail(h, PLAS_ERR_INVALID_ARGUMENT, "batched sorts use the box filter");
   if (st == PLAS_OK && prm.resume != nullptr)
     st = fail(h, PLAS_ERR_INVALID_ARGUMENT, "batched sorts start from their items");
   if (st != PLAS_OK) return st;
@@ -668,8 +681,6 @@ int32_t plas_autotune_batch(plas_handle h, const plas_batch_item* items, int32_t
   if (count >= kMaxSlots) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "too many sorts in one batch");
   plas_sort_params base;
   int32_t st = check_params(h, params, &base);
-  if (st == PLAS_OK && base.filter != PLAS_FILTER_BOX)
-    st = fail(h, PLAS_ERR_INVALID_ARGUMENT, "batched sorts use the box filter");
   if (st == PLAS_OK && base.resume != nullptr)
     st = fail(h, PLAS_ERR_INVALID_ARGUMENT, "batched sorts start from their items");
   if (st != PLAS_OK) return st;
@@ -829,8 +840,6 @@ int32_t plas_server_create(plas_handle h, const plas_sort_params* params, const 
   if (s == nullptr) return fail(h, PLAS_ERR_OUT_OF_MEMORY, "server");
   s->h = h;
   int32_t st = check_params(h, params, &s->prm);
-  if (st == PLAS_OK && s->prm.filter != PLAS_FILTER_BOX)
-    st = fail(h, PLAS_ERR_INVALID_ARGUMENT, "served sorts use the box filter");
   if (st == PLAS_OK && s->prm.resume != nullptr)
     st = fail(h, PLAS_ERR_INVALID_ARGUMENT, "served sorts start from their jobs");
   if (st == PLAS_OK) st = check_config(h, config, &s->cfg);

@@ -1454,11 +1454,11 @@ __device__ __forceinline__ T* global_ptr(U PLAS_GLOBAL* p) {
   return (T*)((T PLAS_GLOBAL*)p);
 }
 
-// The row pass of a reorder first steps the sort's controller from state
-// state_idx ^ 1 to state_idx (the one the reorder then uses).
-__device__ __forceinline__ StepArgs batch_step(const BatchGridView& g, int state_idx, int vertical) {
+// The first row pass of a reorder first steps the sort's controller from
+// state state_idx ^ 1 to state_idx (the one the reorder then uses).
+__device__ __forceinline__ StepArgs batch_step(const BatchGridView& g, int state_idx, bool with_step) {
   StepArgs a{};  // table_cells is a host-side launch-size hint, unused here
-  if (vertical) return a;
+  if (!with_step) return a;
   DevState* states = global_ptr<DevState>(g.states);
   a.in = states + (state_idx ^ 1);
   a.out = states + state_idx;
@@ -1468,20 +1468,30 @@ __device__ __forceinline__ StepArgs batch_step(const BatchGridView& g, int state
   return a;
 }
 
+// A batch blur pass's route (see launch_blur_batch): its axis, source and
+// destination grids (0 G, 1 H, 2 T) and whether it runs the step.
+__device__ __forceinline__ int route_vertical(int route) { return route & 1; }
+__device__ __forceinline__ bool route_step(int route) { return (route >> 5) & 1; }
+template <typename S>
+__device__ __forceinline__ S* route_grid(const BatchGridView& g, int sel) {
+  return global_ptr<S>(sel == 0 ? g.G : sel == 1 ? g.H : g.T);
+}
+
 template <typename S, int DP, int WPB>
 __global__ __launch_bounds__(WPB * 64) void k_blur_staged_batch(const BatchGrid* __restrict__ grids,
                                                                 const uint32_t* __restrict__ map,
-                                                                int state_idx, int vertical) {
+                                                                int state_idx, int route) {
   __shared__ StagedLds<S> s_stage[WPB];
   __shared__ DevState s_st;
   uint32_t local;
   const BatchGridView& g = batch_grid(grids, map, local);
   int r;
-  if (!pass_radius<WPB * 64>(batch_step(g, state_idx, vertical), global_ptr<const DevState>(g.states) + state_idx,
-                             0, local, g.blur_blocks, s_st, r))
+  if (!pass_radius<WPB * 64>(batch_step(g, state_idx, route_step(route)),
+                             global_ptr<const DevState>(g.states) + state_idx, 0, local, g.blur_blocks, s_st, r))
     return;
-  const S* in = global_ptr<const S>(vertical ? g.H : g.G);
-  S* out = global_ptr<S>(vertical ? g.T : g.H);
+  const int vertical = route_vertical(route);
+  const S* in = route_grid<S>(g, (route >> 1) & 3);
+  S* out = route_grid<S>(g, (route >> 3) & 3);
   blur_staged_lines<S, DP, WPB>(in, out, g.w, r, vertical, global_ptr<const float>(g.inv), local, g.blur_blocks,
                                 s_stage);
 }
@@ -1489,16 +1499,17 @@ __global__ __launch_bounds__(WPB * 64) void k_blur_staged_batch(const BatchGrid*
 template <int DP, typename S>
 __global__ __launch_bounds__(kBlock) void k_blur_batch(const BatchGrid* __restrict__ grids,
                                                        const uint32_t* __restrict__ map, int state_idx,
-                                                       int vertical) {
+                                                       int route) {
   __shared__ DevState s_st;
   uint32_t local;
   const BatchGridView& g = batch_grid(grids, map, local);
   int r;
-  if (!pass_radius<kBlock>(batch_step(g, state_idx, vertical), global_ptr<const DevState>(g.states) + state_idx, 0,
-                           local, g.blur_blocks, s_st, r))
+  if (!pass_radius<kBlock>(batch_step(g, state_idx, route_step(route)),
+                           global_ptr<const DevState>(g.states) + state_idx, 0, local, g.blur_blocks, s_st, r))
     return;
-  const S* in = global_ptr<const S>(vertical ? g.H : g.G);
-  S* out = global_ptr<S>(vertical ? g.T : g.H);
+  const int vertical = route_vertical(route);
+  const S* in = route_grid<S>(g, (route >> 1) & 3);
+  S* out = route_grid<S>(g, (route >> 3) & 3);
   const int64_t wave = (static_cast<int64_t>(local) * kBlock + threadIdx.x) >> 6;
   blur_reg_lines<DP, S>(in, out, g.w, r, vertical, global_ptr<const float>(g.inv), wave, threadIdx.x & 63);
 }
@@ -1750,31 +1761,37 @@ int default_assign_blocks_cap() { return PLAS_ASSIGN_MAX_BLOCKS; }
 
 template <typename S, int DP>
 hipError_t blur_batch_dp(const BatchGrid* grids, const uint32_t* map, int blocks, int waves_per_block,
-                         int state_idx, int vertical, hipStream_t stream) {
+                         int state_idx, int route, hipStream_t stream) {
   if constexpr (staged_cells<S, DP>()) {
     switch (waves_per_block) {
       case 1:
-        k_blur_staged_batch<S, DP, 1><<<blocks, 64, 0, stream>>>(grids, map, state_idx, vertical);
+        k_blur_staged_batch<S, DP, 1><<<blocks, 64, 0, stream>>>(grids, map, state_idx, route);
         break;
       case 2:
-        k_blur_staged_batch<S, DP, 2><<<blocks, 128, 0, stream>>>(grids, map, state_idx, vertical);
+        k_blur_staged_batch<S, DP, 2><<<blocks, 128, 0, stream>>>(grids, map, state_idx, route);
         break;
       case 4:
-        k_blur_staged_batch<S, DP, 4><<<blocks, 256, 0, stream>>>(grids, map, state_idx, vertical);
+        k_blur_staged_batch<S, DP, 4><<<blocks, 256, 0, stream>>>(grids, map, state_idx, route);
         break;
       default:
         return hipErrorInvalidValue;
     }
   } else {
-    k_blur_batch<DP, S><<<blocks, kBlock, 0, stream>>>(grids, map, state_idx, vertical);
+    k_blur_batch<DP, S><<<blocks, kBlock, 0, stream>>>(grids, map, state_idx, route);
   }
   return hipGetLastError();
 }
 
+int blur_route(int vertical, int src, int dst, int with_step) {
+  return (vertical & 1) | ((src & 3) << 1) | ((dst & 3) << 3) | ((with_step & 1) << 5);
+}
+
 hipError_t launch_blur_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
-                             int waves_per_block, int state_idx, int vertical, hipStream_t stream) {
+                             int waves_per_block, int state_idx, int route, hipStream_t stream) {
+  const int src = (route >> 1) & 3, dst = (route >> 3) & 3;
+  if (src > 2 || dst < 1 || dst > 2 || src == dst) return hipErrorInvalidValue;
   PLAS_DISPATCH_STORAGE(storage, {
-    PLAS_DISPATCH_DP(dp, return (blur_batch_dp<SV, DPV>(grids, map, blocks, waves_per_block, state_idx, vertical,
+    PLAS_DISPATCH_DP(dp, return (blur_batch_dp<SV, DPV>(grids, map, blocks, waves_per_block, state_idx, route,
                                                         stream)));
   });
   return hipSuccess;

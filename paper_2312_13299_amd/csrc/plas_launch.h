@@ -88,12 +88,16 @@ bool staged_blur(int dp, int storage);
 int batch_blur_blocks(int w, int dp, int storage, int waves_per_block, int64_t max_cells);  // wpb: 1, 2, 4
 int batch_assign_blocks(int64_t max_items, int dp, int storage, int cap);  // cap <= 0: the single-sort default
 int default_assign_blocks_cap();
-// One blur pass (vertical 0: G -> H, 1: H -> T) of every mapped grid, all of
-// dp channels and `storage`, with states[state_idx]; the row pass first
-// steps each grid's controller from states[state_idx ^ 1] to
-// states[state_idx] and fills its grouping table.
+// A batch blur pass's route: its axis (vertical 0: rows, 1: columns), its
+// source and destination grids (0 G, 1 H, 2 T; the destination H or T, not
+// the source) and whether it first steps each grid's controller from
+// states[state_idx ^ 1] to states[state_idx] and fills its grouping table
+// (the first row pass of a reorder).
+int blur_route(int vertical, int src, int dst, int with_step);
+// One blur pass along `route` of every mapped grid, all of dp channels and
+// `storage`, with states[state_idx].
 hipError_t launch_blur_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
-                             int waves_per_block, int state_idx, int vertical, hipStream_t stream);
+                             int waves_per_block, int state_idx, int route, hipStream_t stream);
 hipError_t launch_assign_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
                                int state_idx, hipStream_t stream);
 // out[i] = (done, k) of grids[list[i]].states[state_idx], i < count.

@@ -133,23 +133,35 @@ def test_box3_filter_truncated_at_the_coarsest_levels(env):
     assert np.array_equal(perm.cpu().numpy(), want.perm)
 
 
-def test_box3_filter_is_single_sort_only(env):
+def test_box3_filter_in_batches_and_servers(env):
+    """A batch and a server with the filter give each sort's single-sort
+    result, bit for bit; unknown filters are rejected."""
     torch, plas, ctx, ref = env
-    f = torch.from_numpy(synthetic.gaussian_attributes(64, 1)).cuda()
-    L = plas.library()
-    prm = plas._sort_params(filter="box3")
-    items = (plas.BatchItem * 1)()
+    sides, seeds = [16, 24, 33], [1, 2, 3]
+    feats = [torch.from_numpy(synthetic.gaussian_attributes(s * s, 40 + s)).cuda() for s in sides]
+    alone = [ctx.sort(f, s, seed, filter="box3") for f, s, seed in zip(feats, sides, seeds)]
+    for graph in (False, True):
+        perms, results, _ = ctx.sort_batch(feats, sides=sides, seeds=seeds, filter="box3", graph=graph)
+        for (p1, r1), p, r in zip(alone, perms, results):
+            assert torch.equal(p1, p) and r1.reorders == r.reorders and r1.energy_fixed == r.energy_fixed
+    srv = plas.Server(ctx, memory_budget=1 << 30, filter="box3")
+    ids = [srv.submit(f, s, seed) for f, s, seed in zip(feats, sides, seeds)]
+    done = {}
+    for _ in range(100000):
+        running, waiting = srv.step()
+        for job, st, p, r in srv.poll():
+            assert st == plas.OK
+            done[job] = (p, r)
+        if len(done) == len(ids):
+            break
+    for job, (p1, r1) in zip(ids, alone):
+        p, r = done[job]
+        assert torch.equal(p1, p) and r1.reorders == r.reorders
+    srv.close()
     out = torch.empty(64, dtype=torch.int32, device="cuda")
-    items[0].features = f.data_ptr()
-    items[0].n, items[0].d, items[0].side = 64, 59, 8
-    items[0].perm_out = out.data_ptr()
-    cfg = plas._batch_config(False, 0, False, None)[0]
-    assert L.plas_sort_batch(ctx._h, items, 1, ctypes.byref(prm), ctypes.byref(cfg), None) == \
-        plas.ERR_INVALID_ARGUMENT
-    h = ctypes.c_void_p()
-    assert L.plas_server_create(ctx._h, ctypes.byref(prm), None, 1 << 30, ctypes.byref(h)) == \
-        plas.ERR_INVALID_ARGUMENT
+    f = torch.from_numpy(synthetic.gaussian_attributes(64, 1)).cuda()
     bad = plas._sort_params()
     bad.filter = 2
-    assert L.plas_sort(ctx._h, ctypes.c_void_p(f.data_ptr()), 64, 59, 8, plas.LAYOUT_CN, 0, ctypes.byref(bad),
-                       ctypes.c_void_p(out.data_ptr()), None) == plas.ERR_INVALID_ARGUMENT
+    assert plas.library().plas_sort(ctx._h, ctypes.c_void_p(f.data_ptr()), 64, 59, 8, plas.LAYOUT_CN, 0,
+                                    ctypes.byref(bad), ctypes.c_void_p(out.data_ptr()), None) == \
+        plas.ERR_INVALID_ARGUMENT
