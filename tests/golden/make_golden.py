@@ -32,6 +32,9 @@ CASES = {
     # The runtime experiment of App. C: a random 512 x 512 grid of U(0, 255)
     # RGB values; its VAD is stored as well.
     "sort_512_rgb": dict(side=512, data_seed=synthetic.DATA_SEED_RGB, sort_seed=synthetic.SORT_SEED, rgb=True),
+    # The precision workload: 1448 x 1448, D = 59, working grids in bfloat16.
+    "sort_1448_d59_bf16": dict(side=1448, data_seed=synthetic.DATA_SEED_PRECISION, sort_seed=synthetic.SORT_SEED,
+                               storage_bf16=True),
 }
 
 
@@ -42,7 +45,8 @@ def run(name: str) -> dict:
     F = synthetic.random_rgb_grid(side, c["data_seed"]) if rgb else \
         synthetic.gaussian_attributes(side * side, c["data_seed"])
     t0 = time.time()
-    res = oracle.sort(F, side, c["sort_seed"], energy_cap=1 << 20)
+    bf16 = c.get("storage_bf16", False)
+    res = oracle.sort(F, side, c["sort_seed"], energy_cap=1 << 20, storage_bf16=bf16)
     dt = time.time() - t0
     assert res.status == 0
     energies = np.ascontiguousarray(res.reorder_energy, dtype="<u8")
@@ -54,6 +58,7 @@ def run(name: str) -> dict:
         "sort_seed": c["sort_seed"],
         "generator": ("synthetic.random_rgb_grid" if rgb else "synthetic.gaussian_attributes") +
                      " (channel-major float32)",
+        "storage": "bf16" if bf16 else "f32",
         "reorders": int(res.reorders),
         "levels": int(res.levels),
         "scale_shift": int(res.scale_shift),

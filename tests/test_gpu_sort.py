@@ -78,7 +78,7 @@ def test_scene_1024_truncated_matches_oracle(env, start_radius, max_reorders):
     _compare(res, perm.cpu().numpy(), want)
 
 
-@pytest.mark.parametrize("name", ["sort_256_d59", "sort_1024_d59"])
+@pytest.mark.parametrize("name", ["sort_256_d59", "sort_1024_d59", "sort_1448_d59_bf16"])
 def test_full_sort_matches_stored_oracle_result(env, name):
     torch, plas, ctx, ref = env
     path = os.path.join(GOLDEN, f"{name}.json")
@@ -87,7 +87,7 @@ def test_full_sort_matches_stored_oracle_result(env, name):
     gold = json.load(open(path))
     side = gold["side"]
     F = synthetic.gaussian_attributes(side * side, gold["data_seed"])
-    perm, res = ctx.sort(torch.from_numpy(F).cuda(), side, gold["sort_seed"])
+    perm, res = ctx.sort(torch.from_numpy(F).cuda(), side, gold["sort_seed"], storage=gold.get("storage", "f32"))
     p = perm.cpu().numpy().astype("<i4")
     assert res.reorders == gold["reorders"]
     assert res.levels == gold["levels"]
