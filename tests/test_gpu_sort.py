@@ -78,7 +78,7 @@ def test_scene_1024_truncated_matches_oracle(env, start_radius, max_reorders):
     _compare(res, perm.cpu().numpy(), want)
 
 
-@pytest.mark.parametrize("name", ["sort_256_d59", "sort_1024_d59", "sort_1448_d59_bf16"])
+@pytest.mark.parametrize("name", ["sort_256_d59", "sort_1024_d59", "sort_512_d59_bf16"])
 def test_full_sort_matches_stored_oracle_result(env, name):
     torch, plas, ctx, ref = env
     path = os.path.join(GOLDEN, f"{name}.json")
