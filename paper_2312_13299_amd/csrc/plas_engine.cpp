@@ -207,7 +207,8 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
   const int64_t max_k = reorder_bound(levels.size(), prm.inv_threshold);
   double blur_ms = 0.0, assign_ms = 0.0;
   int64_t timed_reorders = 0;
-  int64_t slots = 0;  // reorder slots queued so far; slot i runs reorder i unless the sort has ended
+  int64_t slots = 0;  // reorder slots queued so far; slot i runs reorder k0 + i unless the sort has ended
+  const int64_t k0 = S->k;  // reorders done before this call (a resumed sort)
   for (;;) {
     for (int i = 0; i < chunk; ++i) {
       // The first row pass steps the controller from states[cur] to
@@ -252,7 +253,7 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
     const int64_t k_now = h->status_host->k;
     if (profile) {
       // Slots at or after the end of the sort returned at once.
-      const int64_t ran = done ? std::max<int64_t>(0, std::min<int64_t>(chunk, k_now - first_slot)) : chunk;
+      const int64_t ran = done ? std::max<int64_t>(0, std::min<int64_t>(chunk, k_now - k0 - first_slot)) : chunk;
       for (int64_t i = 0; i < ran; i += kProfileEvery) {
         float a = 0.0f, b = 0.0f;
         PLAS_HIP(h, hipEventElapsedTime(&a, h->events[4 * i + 0], h->events[4 * i + 1]));
@@ -267,7 +268,7 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
     // short the device state is broken. Also stop at the bound on reorders
     // that the stall test implies (energies strictly fall by at least 1/M per
     // improvement, two stalls end a level).
-    if (k_now < slots - 1 || k_now > max_k)
+    if (k_now - k0 < slots - 1 || k_now > max_k)
       return fail(h, PLAS_ERR_HIP, "device controller made no progress");
   }
 

@@ -134,3 +134,14 @@ def test_batch_checkpoints_equal_single_sort_checkpoints(env):
             a, b = r1.checkpoint, res.checkpoint
             assert bytes(a) == bytes(b), (s, max_reorders)
             assert a.done == (max_reorders == 0)
+
+
+def test_profiled_resume_counts_only_the_reorders_it_ran(env):
+    torch, plas, ctx, ref = env
+    side, seed = 32, 21
+    f = torch.from_numpy(synthetic.gaussian_attributes(side * side, seed)).cuda()
+    perm, res = ctx.sort(f, side, seed, max_reorders=50)
+    p2, r2 = ctx.sort(f, side, seed, init_perm=perm, resume=res.checkpoint, profile=True)
+    ran = r2.reorders - 50
+    # Every 8th reorder slot of this call is timed.
+    assert r2.assign_launches == (ran + 7) // 8 and r2.blur_launches == 2 * r2.assign_launches
