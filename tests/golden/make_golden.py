@@ -32,6 +32,10 @@ CASES = {
     # The runtime experiment of App. C: a random 512 x 512 grid of U(0, 255)
     # RGB values; its VAD is stored as well.
     "sort_512_rgb": dict(side=512, data_seed=synthetic.DATA_SEED_RGB, sort_seed=synthetic.SORT_SEED, rgb=True),
+    # The same grid with the Gaussian-like target filter (three box passes
+    # per axis).
+    "sort_512_rgb_box3": dict(side=512, data_seed=synthetic.DATA_SEED_RGB, sort_seed=synthetic.SORT_SEED, rgb=True,
+                              filter="box3"),
     # A whole sort with the working grids in bfloat16 (the precision
     # workload's storage at a size the oracle finishes in about 20 minutes).
     "sort_512_d59_bf16": dict(side=512, data_seed=synthetic.DATA_SEED_PRECISION, sort_seed=synthetic.SORT_SEED,
@@ -47,7 +51,8 @@ def run(name: str) -> dict:
         synthetic.gaussian_attributes(side * side, c["data_seed"])
     t0 = time.time()
     bf16 = c.get("storage_bf16", False)
-    res = oracle.sort(F, side, c["sort_seed"], energy_cap=1 << 20, storage_bf16=bf16)
+    filt = c.get("filter", "box")
+    res = oracle.sort(F, side, c["sort_seed"], energy_cap=1 << 20, storage_bf16=bf16, filter=filt)
     dt = time.time() - t0
     assert res.status == 0
     energies = np.ascontiguousarray(res.reorder_energy, dtype="<u8")
@@ -60,6 +65,7 @@ def run(name: str) -> dict:
         "generator": ("synthetic.random_rgb_grid" if rgb else "synthetic.gaussian_attributes") +
                      " (channel-major float32)",
         "storage": "bf16" if bf16 else "f32",
+        "filter": filt,
         "reorders": int(res.reorders),
         "levels": int(res.levels),
         "scale_shift": int(res.scale_shift),

@@ -10,7 +10,7 @@ import os
 import pytest
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-NAMES = sorted(f[:-5] for f in os.listdir(GOLDEN) if f.endswith(".json"))
+NAMES = sorted(f[:-5] for f in os.listdir(GOLDEN) if f.startswith("sort_") and f.endswith(".json"))
 
 
 def schedule_levels(w: int) -> int:

@@ -62,16 +62,17 @@ def test_vad_rejects_a_bad_permutation(env):
     assert e.value.status == plas.ERR_INVALID_ARGUMENT
 
 
-def test_rgb_512_sort_matches_stored_oracle_result(env):
+@pytest.mark.parametrize("name", ["sort_512_rgb", "sort_512_rgb_box3"])
+def test_rgb_512_sort_matches_stored_oracle_result(env, name):
     torch, plas, ctx, ref = env
-    path = os.path.join(GOLDEN, "sort_512_rgb.json")
+    path = os.path.join(GOLDEN, f"{name}.json")
     if not os.path.exists(path):
         pytest.skip(f"{path} not generated")
     gold = json.load(open(path))
     side = gold["side"]
     F = synthetic.random_rgb_grid(side, gold["data_seed"])
     f = torch.from_numpy(F).cuda()
-    perm, res = ctx.sort(f, side, gold["sort_seed"])
+    perm, res = ctx.sort(f, side, gold["sort_seed"], filter=gold.get("filter", "box"))
     p = perm.cpu().numpy().astype("<i4")
     assert res.reorders == gold["reorders"] and res.levels == gold["levels"]
     assert res.energy_fixed == int(gold["energy"])
