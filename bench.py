@@ -463,6 +463,14 @@ def main() -> int:
     del src, dst
     roof["copy_gbs"] = round(copy_gbs, 1)
     roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
+    # The whole sort's algorithmic bytes per reorder (two blur passes, the
+    # assignment's reads and its moved-cell writes) over the wall time.
+    e = 2 if precision else 4
+    moved = sum(t["moved"] for t in res.trace) / max(res.reorders, 1)
+    per_reorder = 3 * n * 2 * d * e + moved * (d * e + 8)
+    path_gbs = per_reorder * res.reorders * args.steps / elapsed / 1e9
+    roof["whole_sort"] = {"bytes_per_reorder": int(per_reorder), "achieved": round(path_gbs, 1),
+                          "frac": round(path_gbs / HBM_PEAK_GBS, 4)}
     ms_per_step = elapsed / args.steps * 1e3
     value = n * args.steps / elapsed
     line = {
