@@ -102,6 +102,16 @@ def cpu_baseline(F, side: int, seed: int, reorders_full: int, sample_reorders: i
     per_reorder = dt / max(res.reorders, 1)
     est = per_reorder * reorders_full
     n = side * side
+    # The same oracle on one thread, on a shorter sample (the result does not
+    # depend on the thread count).
+    one_reorders = max(1, sample_reorders // 12)
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    one = oracle.sort(F, side, seed, max_reorders=one_reorders)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(threads)
+    if one.status != 0 or not (one.perm == oracle.sort(F, side, seed, max_reorders=one_reorders).perm).all():
+        raise RuntimeError("oracle result depends on the thread count")
     return {
         "value": n / est,
         "unit": "Gaussians/s",
@@ -110,6 +120,8 @@ def cpu_baseline(F, side: int, seed: int, reorders_full: int, sample_reorders: i
         "sample": (f"CPU oracle on the same {side}x{side} D={F.shape[0]} input, stopped after "
                    f"{res.reorders} reorders in {dt:.1f} s; value = N / ({per_reorder:.3f} s per reorder "
                    f"x {reorders_full} reorders of the full sort)"),
+        "one_thread": {"seconds_per_reorder": round(dt1 / max(one.reorders, 1), 4), "sample_reorders": one.reorders,
+                       "speedup_of_all_cores": round(dt1 / max(one.reorders, 1) / per_reorder, 2)},
     }
 
 

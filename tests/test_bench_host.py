@@ -76,3 +76,12 @@ def test_percentile_nearest_rank():
     assert bench.percentile(v, 0) == 1.0
     assert bench.percentile(list(range(1, 101)), 99) == 99
     assert bench.percentile([7.0], 50) == 7.0
+
+
+def test_cpu_baseline_on_a_small_grid():
+    import synthetic
+    F = synthetic.gaussian_attributes(64 * 64, 1)
+    b = bench.cpu_baseline(F, 64, 0x5EED, 400, 24)
+    assert b["kind"] == "oracle" and b["unit"] == "Gaussians/s" and b["cores"] >= 1
+    assert b["value"] > 0 and "stopped after 24 reorders" in b["sample"]
+    assert b["one_thread"]["sample_reorders"] == 2 and b["one_thread"]["seconds_per_reorder"] > 0
