@@ -507,6 +507,10 @@ def main() -> int:
             "reorders": res.reorders, "levels": res.levels,
             "energy_mean": res.energy,
         },
+        # Per level: radius r, reorders, and the mean squared distance to the
+        # target after the level's last reorder (energy * 2^-s / N).
+        "level_energy": [[t["r"], t["reorders"], round(t["energy"] * 2.0 ** -res.scale_shift / n, 6)]
+                         for t in res.trace],
         "roofline": roof,
     }
     if precision and not args.no_fp32_compare:
