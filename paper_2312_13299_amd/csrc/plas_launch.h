@@ -87,7 +87,7 @@ bool staged_blur(int dp, int storage);
 // max_cells entries at about one entry per thread.
 int batch_blur_blocks(int w, int dp, int storage, int waves_per_block, int64_t max_cells);  // wpb: 1, 2, 4
 int batch_assign_blocks(int64_t max_items, int dp, int storage, int cap);  // cap <= 0: the single-sort default
-int default_assign_blocks_cap();
+int assign_blocks_cap(int storage);  // blocks of an assignment launch without a tuned value
 // A batch blur pass's route: its axis (vertical 0: rows, 1: columns), its
 // source and destination grids (0 G, 1 H, 2 T; the destination H or T, not
 // the source) and whether it first steps each grid's controller from
