@@ -22,6 +22,11 @@ using namespace plas_host;
 namespace {
 
 constexpr int kDefaultWavesPerBlock = 2;  // as plas_sort
+// Assignment blocks per sort when the tuning table names none. A batch
+// launch covers every running sort, so fewer blocks per sort than a lone
+// float32 sort takes (8192) serve it better: 4096 measured best for the
+// 64-grid batch and the served mix.
+constexpr int kBatchAssignBlocks = 4096;
 constexpr int kMaxSlots = 1 << 16;     // grid index field of a block map entry
 constexpr int kMaxLocalBlocks = 1 << 16;  // block index field
 
@@ -276,7 +281,8 @@ class BatchRun {
     g.states = reinterpret_cast<DevState*>(base + o_states);
     g.w = s.w;
     g.blur_blocks = plas::batch_blur_blocks(s.w, s.dp, s.storage, s.wpb, s.max_cells);
-    g.assign_blocks = plas::batch_assign_blocks(s.max_items, s.dp, s.storage, s.assign_cap);
+    g.assign_blocks = plas::batch_assign_blocks(s.max_items, s.dp, s.storage,
+                                                s.assign_cap > 0 ? s.assign_cap : kBatchAssignBlocks);
 
     // Features -> X in T, the start arrangement, G = X[P] (as plas_sort).
     hipStream_t stream = b_->stream;
