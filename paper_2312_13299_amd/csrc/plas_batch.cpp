@@ -22,10 +22,8 @@ using namespace plas_host;
 namespace {
 
 constexpr int kDefaultWavesPerBlock = 2;  // as plas_sort
-// Assignment blocks per sort when the tuning table names none. A batch
-// launch covers every running sort, so fewer blocks per sort than a lone
-// float32 sort takes (8192) serve it better: 4096 measured best for the
-// 64-grid batch and the served mix.
+// Assignment blocks per sort when the tuning table names none (as a lone
+// sort's launch).
 constexpr int kBatchAssignBlocks = 4096;
 constexpr int kMaxSlots = 1 << 16;     // grid index field of a block map entry
 constexpr int kMaxLocalBlocks = 1 << 16;  // block index field
