@@ -41,7 +41,7 @@ extern "C" {
 /* Status codes. */
 #define PLAS_OK 0
 #define PLAS_ERR_INVALID_ARGUMENT (-1) /* NULL pointer, n != side^2, side < 2, bad d/layout/radius, init_perm not a bijection */
-#define PLAS_ERR_UNSUPPORTED (-2)      /* a dtype or channel count this build does not handle */
+#define PLAS_ERR_UNSUPPORTED (-2)      /* a dtype or channel count the library does not handle */
 #define PLAS_ERR_OUT_OF_MEMORY (-3)    /* the device workspace could not be allocated */
 #define PLAS_ERR_HIP (-4)              /* a HIP runtime call failed; see plas_last_error */
 #define PLAS_ERR_NONFINITE (-5)        /* a feature value is NaN or infinite */
