@@ -419,7 +419,7 @@ def main() -> int:
     torch.cuda.synchronize()
 
     # Timed region: K whole sorts. The library times the blur and assignment
-    # launches of every 8th reorder with HIP events on its stream
+    # launches of every 32nd reorder with HIP events on its stream
     # (profile=True).
     results = []
     torch.cuda.synchronize()
@@ -455,7 +455,7 @@ def main() -> int:
         "per_launch_bytes": int(kern[dominant]["bytes"]),
         "avg_launch_ms": round(kern[dominant]["avg_ms"], 5),
         "timed_launches": int(agg.blur_launches if dominant == "blur_pass" else agg.assign_launches),
-        "sample": "every 8th reorder of the timed sorts, HIP events on the library's stream",
+        "sample": "every 32nd reorder of the timed sorts, HIP events on the library's stream",
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
     }

@@ -116,7 +116,7 @@ typedef struct {
     int64_t max_reorders;    /* 0: run the whole schedule; > 0: stop after this many reorders */
     const int32_t* init_perm;/* device int32[n] start arrangement (gather form), or NULL for the seeded random start */
     int32_t min_block;       /* smallest block side; 16 */
-    int32_t profile;         /* nonzero: time the blur and assignment kernels of every 8th reorder with HIP events (fills *_ms and *_launches in stats) */
+    int32_t profile;         /* nonzero: time the blur and assignment kernels of every 32nd reorder with HIP events (fills *_ms and *_launches in stats) */
     int32_t reorders_per_sync; /* reorders queued between checks of the device's done flag; 0: library default */
     int32_t storage;         /* PLAS_STORAGE_F32 (default) or PLAS_STORAGE_BF16 */
     int32_t filter;          /* PLAS_FILTER_BOX (default) or PLAS_FILTER_BOX3 */
@@ -146,10 +146,11 @@ typedef struct {
     int32_t trace_cap;      /* its capacity */
     int32_t reserved;
     /* With params->profile: device time summed over the timed launches (every
-     * 8th reorder; each event costs device time, so not every one is timed),
+     * 32nd reorder slot of each chunk; each event costs device time, so not
+     * every one is timed),
      * and how many launches that was. Average = *_ms / *_launches. */
     double blur_ms;         /* both blur passes */
-    int64_t blur_launches;  /* passes (two per reorder) */
+    int64_t blur_launches;  /* passes (two per reorder, six with PLAS_FILTER_BOX3) */
     double assign_ms;       /* assignment kernel */
     int64_t assign_launches;
     double total_ms;        /* wall time of the whole call */

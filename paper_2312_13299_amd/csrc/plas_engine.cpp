@@ -201,7 +201,7 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
   const int passes = prm.filter == PLAS_FILTER_BOX3 ? 3 : 1;  // box passes per axis
   const bool profile = prm.profile != 0;
   if (profile) {
-    st = ensure_events(h, static_cast<size_t>(chunk) * 4);
+    st = ensure_events(h, static_cast<size_t>(chunk) * 3);
     if (st != PLAS_OK) return st;
   }
   const int64_t max_k = reorder_bound(levels.size(), prm.inv_threshold);
@@ -221,7 +221,7 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
       const plas::StepArgs step{&states[cur], Sd, Ld, Td, table, max_cells};
       cur ^= 1;
       const bool timed = profile && i % kProfileEvery == 0;
-      if (timed) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 0], h->stream));
+      if (timed) PLAS_HIP(h, hipEventRecord(h->events[3 * i + 0], h->stream));
       void* bufs[2] = {H, T};
       const void* src = G;
       for (int p = 0; p < passes; ++p) {
@@ -235,10 +235,10 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
         PLAS_HIP(h, plas::launch_blur_pass(src, dst, w, dp, storage, Sd, 0, 1, as<float>(h->inv), h->stream));
         src = dst;
       }
-      if (timed) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 1], h->stream));
-      if (timed) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 2], h->stream));
+      // One event ends the blur passes and starts the assignment.
+      if (timed) PLAS_HIP(h, hipEventRecord(h->events[3 * i + 1], h->stream));
       PLAS_HIP(h, plas::launch_assign(G, T, P, table, Sd, dp, storage, max_items, h->stream));
-      if (timed) PLAS_HIP(h, hipEventRecord(h->events[4 * i + 3], h->stream));
+      if (timed) PLAS_HIP(h, hipEventRecord(h->events[3 * i + 2], h->stream));
     }
     const int64_t first_slot = slots;
     slots += chunk;
@@ -256,8 +256,8 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
       const int64_t ran = done ? std::max<int64_t>(0, std::min<int64_t>(chunk, k_now - k0 - first_slot)) : chunk;
       for (int64_t i = 0; i < ran; i += kProfileEvery) {
         float a = 0.0f, b = 0.0f;
-        PLAS_HIP(h, hipEventElapsedTime(&a, h->events[4 * i + 0], h->events[4 * i + 1]));
-        PLAS_HIP(h, hipEventElapsedTime(&b, h->events[4 * i + 2], h->events[4 * i + 3]));
+        PLAS_HIP(h, hipEventElapsedTime(&a, h->events[3 * i + 0], h->events[3 * i + 1]));
+        PLAS_HIP(h, hipEventElapsedTime(&b, h->events[3 * i + 1], h->events[3 * i + 2]));
         blur_ms += a;
         assign_ms += b;
         ++timed_reorders;

@@ -140,8 +140,13 @@ def test_chunking_does_not_change_the_result(env):
     c, rc = ctx.sort(F, side, 4, profile=True)
     assert torch.equal(a, b) and torch.equal(a, c)
     assert ra.reorders == rb.reorders == rc.reorders
-    # Profiling times every 8th reorder (slots 0, 8, 16, 24 of each chunk of 32).
-    assert rc.assign_launches == (rc.reorders + 7) // 8 and rc.blur_launches == 2 * rc.assign_launches
+    # Profiling times every 32nd reorder slot of a chunk: slot 0 of each chunk of 32.
+    assert rc.assign_launches == (rc.reorders + 31) // 32 and rc.blur_launches == 2 * rc.assign_launches
+    # With 97 reorders per chunk: slots 0, 32, 64 and 96 of each chunk.
+    d, rd = ctx.sort(F, side, 4, reorders_per_sync=97, profile=True)
+    assert torch.equal(a, d)
+    full, tail = divmod(rd.reorders, 97)
+    assert rd.assign_launches == 4 * full + (tail + 31) // 32
     assert rc.assign_ms > 0 and rc.blur_ms > 0
 
 
