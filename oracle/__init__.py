@@ -54,6 +54,19 @@ class State(ctypes.Structure):
     ]
 
 
+class Control(ctypes.Structure):
+    """The progress-control state of one radius level (plas_ref_ctl)."""
+    _fields_ = [
+        ("has_prev", ctypes.c_int32),
+        ("just_shifted", ctypes.c_int32),
+        ("E_prev", ctypes.c_uint64),
+    ]
+
+
+# Actions of plas_ref_control.
+CTL_KEEP, CTL_SHIFT, CTL_END = 0, 1, 2
+
+
 class _Params(ctypes.Structure):
     _fields_ = [
         ("seed", ctypes.c_uint64),
@@ -157,6 +170,10 @@ def lib() -> ctypes.CDLL:
             "plas_ref_vad": (ctypes.c_double, [vp, vp, ctypes.c_int64, ctypes.c_int32,
                                                ctypes.c_int32, ctypes.c_int32]),
             "plas_ref_set_threads": (ctypes.c_int32, [ctypes.c_int32]),
+            "plas_ref_improved": (ctypes.c_int32, [ctypes.c_uint64, ctypes.c_uint64,
+                                                   ctypes.c_int32, ctypes.c_uint32]),
+            "plas_ref_control": (ctypes.c_int32, [ctypes.POINTER(Control), ctypes.c_uint64,
+                                                  ctypes.c_uint32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -396,6 +413,17 @@ def vad(F: np.ndarray, perm: np.ndarray | None, side: int, layout: str = "cn") -
     n, d = _nd(F, layout)
     p = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
     return float(lib().plas_ref_vad(_ptr(F), _ptr(p), n, d, side, LAYOUTS[layout]))
+
+
+def improved(E: int, E_prev: int, has_prev: bool, M: int) -> bool:
+    """The oracle's improvement test for one reorder's energy E."""
+    return bool(lib().plas_ref_improved(E, E_prev, 1 if has_prev else 0, M))
+
+
+def control(state: Control, E: int, M: int) -> int:
+    """Applies E to the level's control state in place; returns CTL_KEEP,
+    CTL_SHIFT or CTL_END."""
+    return int(lib().plas_ref_control(ctypes.byref(state), E, M))
 
 
 def set_threads(threads: int) -> int:

@@ -120,7 +120,7 @@ uint64_t plas_ref_fmix64(uint64_t k)
 /* round function                                                            */
 /* F(R, K) = fmix64(R xor K) mod 2^h, and cycle walking (Black and Rogaway,  */
 /* "Ciphers with Arbitrary Finite Domains", 2002) down to [0, n).            */
-/* Pinned: bijective for every n up to 2^12 and sampled larger n; key        */
+/* Pinned: bijective for every n up to 2^16 and sampled larger n; key        */
 /* dependent; statistically uniform.                                         */
 /* ------------------------------------------------------------------------ */
 
@@ -625,14 +625,53 @@ static int is_bijection(const int32_t* perm, int64_t n)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Progress control between reorders of one radius level (Sec. 3.1): after  */
+/* each assignment the distance to the target is compared with the previous */
+/* one; an improvement of less than 0.01 % counts as none. Then a new block */
+/* position is drawn, and if the reorder with that position does not        */
+/* improve either, the level ends and the radius shrinks.                   */
+/* Readings: the distance is the integer energy E; with M = 10^4 a reorder  */
+/* improves iff E < E_prev and E_prev - E >= ceil(E_prev / M), which for    */
+/* integers is exactly (E_prev - E) / E_prev >= 1 / M, evaluated without a  */
+/* 128-bit product. The first reorder of a level has nothing to compare     */
+/* with and counts as an improvement. After a stall the stalled energy is   */
+/* the one the next reorder must beat.                                      */
+/* Pinned: against exact rational arithmetic at and around the threshold,  */
+/* on hand-worked energy sequences, and by replaying whole sorts' energies. */
+/* ------------------------------------------------------------------------ */
+
+int32_t plas_ref_improved(uint64_t E, uint64_t E_prev, int32_t has_prev, uint32_t M)
+{
+    if (!has_prev)
+        return 1;
+    if (M < 1 || E >= E_prev)
+        return 0;
+    uint64_t need = E_prev / M + (E_prev % M != 0); /* ceil(E_prev / M) */
+    return E_prev - E >= need;
+}
+
+int32_t plas_ref_control(plas_ref_ctl* c, uint64_t E, uint32_t M)
+{
+    if (plas_ref_improved(E, c->E_prev, c->has_prev, M)) {
+        c->E_prev = E;
+        c->has_prev = 1;
+        c->just_shifted = 0;
+        return PLAS_REF_CTL_KEEP;
+    }
+    if (c->just_shifted)
+        return PLAS_REF_CTL_END;
+    c->just_shifted = 1;
+    c->E_prev = E;
+    return PLAS_REF_CTL_SHIFT;
+}
+
+/* ------------------------------------------------------------------------ */
 /* The sort (Sec. 3.1). Control, per level:                                  */
 /*  - draw a block shift; no previous energy yet;                            */
 /*  - each reorder: target = blur(grid), then one blockwise assignment;      */
-/*  - improved means: no previous energy, or E < E_prev and                  */
-/*    E_prev - E >= ceil(E_prev / M) with M = 10^4 (the 0.01 % threshold);   */
-/*  - improved: remember E, carry on with the same shift;                    */
-/*  - not improved right after a new shift: the level ends;                  */
-/*  - not improved otherwise: draw a new shift, remember E.                  */
+/*  - after it, plas_ref_control: improved (see above) keeps the shift;      */
+/*    a first stall draws a new shift; a stall right after a new shift ends  */
+/*    the level.                                                             */
 /* The grouping permutation is drawn anew for every reorder k (purpose 1),   */
 /* the shift for every shift draw j (purpose 2), the start arrangement once  */
 /* (purpose 0).                                                              */
@@ -727,17 +766,16 @@ int32_t plas_ref_sort(const float* F, int64_t n, int32_t d, int32_t side, int32_
         if (beta > w)
             beta = w;
         int32_t dy, dx;
-        int has_prev = 0, just_shifted = 0;
-        uint64_t E_prev = 0;
+        plas_ref_ctl ctl = {0, 0, 0};
         int64_t level_reorders = 0;
         uint64_t level_moved = 0;
         if (resume_in_level) {
             /* Inside a level: its shift and stall state as they were. */
             dy = R->dy;
             dx = R->dx;
-            has_prev = R->has_prev != 0;
-            just_shifted = R->just_shifted != 0;
-            E_prev = R->E_prev;
+            ctl.has_prev = R->has_prev != 0;
+            ctl.just_shifted = R->just_shifted != 0;
+            ctl.E_prev = R->E_prev;
             level_reorders = R->level_reorders;
             level_moved = R->level_moved;
             resume_in_level = 0;
@@ -752,9 +790,9 @@ int32_t plas_ref_sort(const float* F, int64_t n, int32_t d, int32_t side, int32_
                 at.levels_run = levels;
                 at.dy = dy;
                 at.dx = dx;
-                at.has_prev = has_prev;
-                at.just_shifted = just_shifted;
-                at.E_prev = E_prev;
+                at.has_prev = ctl.has_prev;
+                at.just_shifted = ctl.just_shifted;
+                at.E_prev = ctl.E_prev;
                 at.level_reorders = level_reorders;
                 at.level_moved = level_moved;
                 break;
@@ -770,18 +808,12 @@ int32_t plas_ref_sort(const float* F, int64_t n, int32_t d, int32_t side, int32_
             level_reorders++;
             level_moved += moved;
             E_last = E;
-            int improved = !has_prev || (E < E_prev && E_prev - E >= (E_prev + M - 1) / M);
-            if (improved) {
-                E_prev = E;
-                has_prev = 1;
-                just_shifted = 0;
-            } else if (just_shifted) {
+            int32_t act = plas_ref_control(&ctl, E, M);
+            if (act == PLAS_REF_CTL_END)
                 break;
-            } else {
+            if (act == PLAS_REF_CTL_SHIFT) {
                 plas_ref_shift(prm->seed, j, w, &dy, &dx);
                 j++;
-                just_shifted = 1;
-                E_prev = E;
             }
         }
         if (level_reorders > 0) {

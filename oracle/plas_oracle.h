@@ -145,6 +145,24 @@ int32_t plas_ref_schedule(int32_t w, double decay, int32_t min_block, double sta
 int32_t plas_ref_gather(const float* F, const int32_t* perm, int64_t n, int32_t d,
                         int32_t layout, float* G);
 
+/* Progress control inside one radius level (Sec. 3.1). */
+typedef struct {
+    int32_t has_prev;      /* the level has an energy to compare the next one with */
+    int32_t just_shifted;  /* the last reorder stalled and a new shift was drawn */
+    uint64_t E_prev;       /* the energy the next reorder is compared with */
+} plas_ref_ctl;
+
+#define PLAS_REF_CTL_KEEP 0  /* improved: the next reorder keeps the block shift */
+#define PLAS_REF_CTL_SHIFT 1 /* first stall: draw a new block shift */
+#define PLAS_REF_CTL_END 2   /* stall right after a new shift: the level ends */
+
+/* 1 iff a reorder with energy E improves on E_prev by at least 1/M of it
+ * (always 1 when there is no previous energy), else 0. */
+int32_t plas_ref_improved(uint64_t E, uint64_t E_prev, int32_t has_prev, uint32_t M);
+/* Applies a reorder's energy E to the level's control state c and returns
+ * the action: KEEP, SHIFT or END. A new level starts from {0, 0, 0}. */
+int32_t plas_ref_control(plas_ref_ctl* c, uint64_t E, uint32_t M);
+
 /* The whole sort. */
 int32_t plas_ref_sort(const float* F, int64_t n, int32_t d, int32_t side, int32_t layout,
                       const plas_ref_params* params, int32_t* perm_out, plas_ref_result* res);

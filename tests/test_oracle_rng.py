@@ -95,6 +95,19 @@ def test_bijection_exhaustive_small_n(ref, keyseed):
         assert np.array_equal(np.sort(table), np.arange(n)), n
 
 
+@pytest.mark.slow
+def test_bijection_exhaustive_every_n_to_65536(ref):
+    # Every domain size up to 2^16 (grouping tables up to beta = 256 and
+    # every grid up to 256 x 256), each with its own keys: the table is a
+    # permutation of [0, n).
+    for n in range(1, (1 << 16) + 1):
+        table = ref.bijection_table(n, ref.draw(0xB1, 3, n))
+        assert table.min() == 0 and table.max() == n - 1, n
+        seen = np.zeros(n, dtype=bool)
+        seen[table] = True
+        assert seen.all(), n
+
+
 @pytest.mark.parametrize("n", [256 * 256, 1 << 18, 1024 * 1024, 1448 * 1448, 1000 * 1001])
 def test_bijection_large_n(ref, n):
     rk = ref.draw(7, 0, 0)
