@@ -80,8 +80,8 @@ typedef struct {
     double loop_ms;         /* the reorder loop */
     double total_ms;        /* the whole call */
     double step_ms;         /* with config->profile: summed device times per launch kind; the
-                               controller step runs inside the row blur, so step_ms stays ~0
-                               and blur_ms includes it */
+                               controller step runs at the end of the assignment, so step_ms
+                               stays 0 and assign_ms includes it */
     double blur_ms;
     double assign_ms;
 } plas_batch_stats;

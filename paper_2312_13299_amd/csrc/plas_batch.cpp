@@ -4,7 +4,7 @@
 // chunks of reorders and a measured table of launch shapes.
 //
 // Each sort owns one device allocation (its three grids, permutation,
-// grouping table, inverse counts, level table, trace and state pair) and a
+// grouping table, inverse counts, level table, trace and state) and a
 // slot in the batch's descriptor array. Whenever the set of running sorts
 // changes, the host rebuilds the launch plan -- the descriptors, the list of
 // running slots and one block map per launch -- and uploads it in one copy.
@@ -34,7 +34,7 @@ enum LaunchKind { kBlur = 1, kAssign = 2 };
 
 // Byte offsets of one sort's buffers in its allocation.
 struct SortLayout {
-  size_t g, h, t, p, table, inv, levels, trace, states, bytes;
+  size_t g, h, t, p, table, inv, levels, trace, state, bytes;
 };
 
 SortLayout sort_layout(int32_t w, int dp, int32_t storage, size_t nlevels, int64_t max_cells) {
@@ -58,8 +58,8 @@ SortLayout sort_layout(int32_t w, int dp, int32_t storage, size_t nlevels, int64
   off = align_up(off + nlevels * sizeof(LevelInfo));
   L.trace = off;
   off = align_up(off + nlevels * sizeof(plas_level_out));
-  L.states = off;
-  off = align_up(off + 2 * sizeof(DevState));
+  L.state = off;
+  off = align_up(off + sizeof(DevState));
   L.bytes = off;
   return L;
 }
@@ -202,7 +202,6 @@ class BatchRun {
       routes_.push_back(plas::blur_route(1, src, dst, 0));
       src = dst;
     }
-    if (graph_ && (chunk_ & 1)) ++chunk_;  // a replay must end on the parity it started on
   }
   ~BatchRun() {
     drop_graph();
@@ -263,7 +262,7 @@ class BatchRun {
     const SortLayout lay = sort_layout(s.w, s.dp, s.storage, s.levels.size(), s.max_cells);
     const size_t nl = s.levels.size();
     const size_t o_g = lay.g, o_h = lay.h, o_t = lay.t, o_p = lay.p, o_table = lay.table, o_inv = lay.inv,
-                 o_levels = lay.levels, o_trace = lay.trace, o_states = lay.states;
+                 o_levels = lay.levels, o_trace = lay.trace, o_state = lay.state;
     s.footprint = static_cast<int64_t>(lay.bytes);
     PLAS_HIP(h_, reserve(s.mem, lay.bytes));
     char* base = static_cast<char*>(s.mem.ptr);
@@ -276,7 +275,7 @@ class BatchRun {
     g.inv = reinterpret_cast<const float*>(base + o_inv);
     g.levels = reinterpret_cast<const LevelInfo*>(base + o_levels);
     g.trace = reinterpret_cast<plas_level_out*>(base + o_trace);
-    g.states = reinterpret_cast<DevState*>(base + o_states);
+    g.state = reinterpret_cast<DevState*>(base + o_state);
     g.w = s.w;
     g.blur_blocks = plas::batch_blur_blocks(s.w, s.dp, s.storage, s.wpb, s.max_cells);
     g.assign_blocks = plas::batch_assign_blocks(s.max_items, s.dp, s.storage,
@@ -305,8 +304,7 @@ class BatchRun {
     DevState* S = h_->state_host;
     plas_sort_params prm = prm_;
     init_sort_state(S, s.w, s.s, s.levels, prm, it.seed);
-    // The next chunk's first step reads states[cur_].
-    PLAS_HIP(h_, hipMemcpyAsync(g.states + cur_, S, sizeof(DevState), hipMemcpyHostToDevice, stream));
+    PLAS_HIP(h_, hipMemcpyAsync(g.state, S, sizeof(DevState), hipMemcpyHostToDevice, stream));
     // The host sources above are freed or reused at return.
     PLAS_HIP(h_, hipStreamSynchronize(stream));
     s.running = true;
@@ -349,7 +347,7 @@ class BatchRun {
     ++chunks;
     slots += chunk_;
     const int nrun = static_cast<int>(run_list_.size());
-    PLAS_HIP(h_, plas::launch_batch_status(grids, list_dev_, nrun, cur_, static_cast<HostStatus*>(b_->status.ptr),
+    PLAS_HIP(h_, plas::launch_batch_status(grids, list_dev_, nrun, static_cast<HostStatus*>(b_->status.ptr),
                                            stream));
     PLAS_HIP(h_, hipMemcpyAsync(b_->status_host, b_->status.ptr, nrun * sizeof(HostStatus), hipMemcpyDeviceToHost,
                                 stream));
@@ -357,11 +355,9 @@ class BatchRun {
     PLAS_HIP(h_, hipStreamSynchronize(stream));
     if (cfg_.profile) {
       for (int i = 0; i < chunk_; ++i) {
-        float a = 0.0f, b = 0.0f, c = 0.0f;
-        PLAS_HIP(h_, hipEventElapsedTime(&a, b_->events[4 * i + 0], b_->events[4 * i + 1]));
-        PLAS_HIP(h_, hipEventElapsedTime(&b, b_->events[4 * i + 1], b_->events[4 * i + 2]));
-        PLAS_HIP(h_, hipEventElapsedTime(&c, b_->events[4 * i + 2], b_->events[4 * i + 3]));
-        step_ms += a;
+        float b = 0.0f, c = 0.0f;
+        PLAS_HIP(h_, hipEventElapsedTime(&b, b_->events[3 * i + 0], b_->events[3 * i + 1]));
+        PLAS_HIP(h_, hipEventElapsedTime(&c, b_->events[3 * i + 1], b_->events[3 * i + 2]));
         blur_ms += b;
         assign_ms += c;
       }
@@ -378,8 +374,8 @@ class BatchRun {
         finished_.push_back(s.tag);
         continue;
       }
-      // Every queued slot but the last has been controlled by now.
-      if (hs.k < s.slots - 1 || hs.k > s.max_k)
+      // Every queued slot has run and been controlled by now.
+      if (hs.k != s.slots || hs.k > s.max_k)
         return fail(h_, PLAS_ERR_HIP, "device controller made no progress");
     }
     return PLAS_OK;
@@ -425,7 +421,7 @@ class BatchRun {
   // Write a finished sort's permutation and stats and free its memory.
   int32_t finish(Sort& s) {
     hipStream_t stream = b_->stream;
-    const DevState* Sd = s.grid.states + cur_;
+    const DevState* Sd = s.grid.state;
     PLAS_HIP(h_, hipMemcpyAsync(s.item.perm_out, s.grid.P, static_cast<size_t>(s.n) * sizeof(int32_t),
                                 hipMemcpyDeviceToDevice, stream));
     DevState* S = h_->state_host;
@@ -525,7 +521,7 @@ class BatchRun {
     for (const Launch& L : launches_) per_reorder += L.kind == kBlur ? static_cast<int>(routes_.size()) : 1;
     launches_per_chunk_ = static_cast<int64_t>(per_reorder) * chunk_;
     if (cfg_.profile) {
-      while (b_->events.size() < static_cast<size_t>(4 * chunk_)) {
+      while (b_->events.size() < static_cast<size_t>(3 * chunk_)) {
         hipEvent_t e;
         PLAS_HIP(h_, hipEventCreate(&e));
         b_->events.push_back(e);
@@ -535,8 +531,8 @@ class BatchRun {
     return PLAS_OK;
   }
 
-  // chunk_ reorders: blur rows (after each sort's controller step from
-  // states[cur] to states[cur ^ 1]), blur columns, assignment, each over all
+  // chunk_ reorders: blur rows (then each sort's grouping table), blur
+  // columns, assignment (then each sort's control step), each over all
   // running sorts.
   int32_t enqueue_reorders(bool timed) {
     hipStream_t stream = b_->stream;
@@ -544,19 +540,17 @@ class BatchRun {
     const plas::BatchGrid* grids = reinterpret_cast<const plas::BatchGrid*>(plan);
     auto map_of = [&](const Launch& L) { return reinterpret_cast<const uint32_t*>(plan + L.map_off); };
     for (int i = 0; i < chunk_; ++i) {
-      if (timed) PLAS_HIP(h_, hipEventRecord(b_->events[4 * i + 0], stream));
-      cur_ ^= 1;
-      if (timed) PLAS_HIP(h_, hipEventRecord(b_->events[4 * i + 1], stream));
+      if (timed) PLAS_HIP(h_, hipEventRecord(b_->events[3 * i + 0], stream));
       for (const int route : routes_)
         for (const Launch& L : launches_)
           if (L.kind == kBlur)
             PLAS_HIP(h_, plas::launch_blur_batch(grids, map_of(L), L.blocks, L.dp, L.storage, L.wpb == 0 ? 4 : L.wpb,
-                                                 cur_, route, stream));
-      if (timed) PLAS_HIP(h_, hipEventRecord(b_->events[4 * i + 2], stream));
+                                                 route, stream));
+      if (timed) PLAS_HIP(h_, hipEventRecord(b_->events[3 * i + 1], stream));
       for (const Launch& L : launches_)
         if (L.kind == kAssign)
-          PLAS_HIP(h_, plas::launch_assign_batch(grids, map_of(L), L.blocks, L.dp, L.storage, cur_, stream));
-      if (timed) PLAS_HIP(h_, hipEventRecord(b_->events[4 * i + 3], stream));
+          PLAS_HIP(h_, plas::launch_assign_batch(grids, map_of(L), L.blocks, L.dp, L.storage, stream));
+      if (timed) PLAS_HIP(h_, hipEventRecord(b_->events[3 * i + 2], stream));
     }
     return PLAS_OK;
   }
@@ -570,7 +564,6 @@ class BatchRun {
   std::vector<int> routes_;  // blur passes of a reorder, in order
   bool graph_ = false;
   bool dirty_ = true;
-  int cur_ = 0;  // state read by the next chunk's first step
   std::vector<Sort> sorts_;
   std::vector<int> run_list_;
   std::vector<Launch> launches_;

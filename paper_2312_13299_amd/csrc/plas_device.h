@@ -24,8 +24,8 @@ struct LevelInfo {
 };
 
 // Device-resident state of one sort. The parameters block is what every
-// kernel of a reorder reads; the control block is owned by the controller
-// kernel, which runs once after each reorder.
+// kernel of a reorder reads; the control block is updated once after each
+// reorder, by the last block of its assignment launch to finish.
 struct DevState {
   // ---- parameters of the current reorder
   int32_t done;
@@ -50,7 +50,7 @@ struct DevState {
   int32_t just_shifted;
   int32_t levels_run;
   uint32_t inv_threshold;
-  int32_t pending;  // a reorder has run whose result the controller has not seen
+  uint32_t blocks_done;  // assignment blocks of the running reorder that have added their sums
   int32_t ended;    // the schedule ended (done for another reason: max_reorders)
   int64_t k;  // reorders done
   int64_t max_reorders;
@@ -71,9 +71,8 @@ struct HostStatus {
 
 struct plas_level_out;
 
-// One sort of a batch: its buffers, its two states (each reorder's
-// controller step reads one and writes the other), and how many blocks of
-// each launch kind it takes. Grids G, H, T are [w*w][dp] in the batch's
+// One sort of a batch: its buffers, its state, and how many blocks of each
+// launch kind it takes. Grids G, H, T are [w*w][dp] in the batch's
 // storage.
 struct BatchGrid {
   void* G;
@@ -84,7 +83,7 @@ struct BatchGrid {
   const float* inv;
   const LevelInfo* levels;
   plas_level_out* trace;
-  DevState* states;
+  DevState* state;
   int32_t w;
   int32_t blur_blocks;
   int32_t assign_blocks;

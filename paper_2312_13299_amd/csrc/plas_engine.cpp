@@ -4,11 +4,12 @@
 //
 // A sort runs entirely on the device. The host prepares the radius schedule
 // (it depends only on the grid side), uploads the first reorder's
-// parameters, and then queues reorders in chunks: blur rows, blur columns,
-// grouping table, assignment, controller. The controller kernel owns the
-// data-dependent control flow (stall test, new block shift, next radius), so
-// the host only reads a small status block between chunks to learn whether
-// the device has finished; kernels queued after the end return at once.
+// parameters, and then queues reorders in chunks: blur rows (which then fill
+// the grouping table), blur columns, assignment. The last block of each
+// assignment runs the control step (stall test, new block shift, next
+// radius), so the data-dependent control flow stays on the device and the
+// host only reads a small status block between chunks to learn whether the
+// device has finished; kernels queued after the end return at once.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -84,7 +85,7 @@ int32_t plas_create(plas_handle* out, int32_t device) {
             hipHostMalloc(reinterpret_cast<void**>(&h->range_host), (2 * 64 + 1) * sizeof(float)) == hipSuccess &&
             hipHostMalloc(reinterpret_cast<void**>(&h->u64_host), 16 * sizeof(unsigned long long)) == hipSuccess &&
             hipHostMalloc(reinterpret_cast<void**>(&h->state_host), sizeof(DevState)) == hipSuccess &&
-            reserve(h->state, 2 * sizeof(DevState)) == hipSuccess &&
+            reserve(h->state, sizeof(DevState)) == hipSuccess &&
             reserve(h->stage_state, sizeof(DevState)) == hipSuccess &&
             reserve(h->scratch, 16 * sizeof(unsigned long long)) == hipSuccess;
   if (!ok) {
@@ -188,15 +189,16 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
     st = apply_checkpoint(h, S, *prm.resume, levels);
     if (st != PLAS_OK) return st;
   }
-  // State buffers: each reorder's step launch reads states[cur] and writes
-  // states[cur ^ 1], which the reorder's kernels then use.
-  DevState* states = as<DevState>(h->state);
-  int cur = 0;
-  PLAS_HIP(h, hipMemcpyAsync(&states[0], S, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
+  // The state: the parameters of the next reorder and the controller. Each
+  // reorder's assignment ends with the control step, run on it in place.
+  DevState* Sd = as<DevState>(h->state);
+  PLAS_HIP(h, hipMemcpyAsync(Sd, S, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
 
   const LevelInfo* Ld = as<LevelInfo>(h->levels);
   plas_level_out* Td = as<plas_level_out>(h->trace);
   int32_t* table = as<int32_t>(h->table);
+  const plas::TableArgs table_fill{table, max_cells};
+  const plas::ControlArgs control{Ld, Td};
   const int chunk = prm.reorders_per_sync > 0 ? prm.reorders_per_sync : kDefaultReordersPerSync;
   const int passes = prm.filter == PLAS_FILTER_BOX3 ? 3 : 1;  // box passes per axis
   const bool profile = prm.profile != 0;
@@ -211,23 +213,18 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
   const int64_t k0 = S->k;  // reorders done before this call (a resumed sort)
   for (;;) {
     for (int i = 0; i < chunk; ++i) {
-      // The first row pass steps the controller from states[cur] to
-      // states[cur ^ 1] (and fills the grouping table); the rest of the
-      // reorder uses states[cur ^ 1]. Each axis takes `passes` box passes
-      // (PLAS_FILTER_BOX3: three), through H and T in turn, the last
-      // column pass writing T: rows G -> H [-> T -> H], columns [H -> T ->
-      // H ->] H -> T.
-      DevState* Sd = &states[cur ^ 1];
-      const plas::StepArgs step{&states[cur], Sd, Ld, Td, table, max_cells};
-      cur ^= 1;
+      // Each axis takes `passes` box passes (PLAS_FILTER_BOX3: three),
+      // through H and T in turn, the last column pass writing T: rows G -> H
+      // [-> T -> H], columns [H -> T -> H ->] H -> T. The first row pass
+      // fills the grouping table after its lines.
       const bool timed = profile && i % kProfileEvery == 0;
       if (timed) PLAS_HIP(h, hipEventRecord(h->events[3 * i + 0], h->stream));
       void* bufs[2] = {H, T};
       const void* src = G;
       for (int p = 0; p < passes; ++p) {
         void* dst = bufs[p & 1];
-        PLAS_HIP(h, plas::launch_blur_pass(src, dst, w, dp, storage, p == 0 ? nullptr : Sd, 0, 0,
-                                           as<float>(h->inv), h->stream, p == 0 ? &step : nullptr));
+        PLAS_HIP(h, plas::launch_blur_pass(src, dst, w, dp, storage, Sd, 0, 0, as<float>(h->inv), h->stream,
+                                           p == 0 ? &table_fill : nullptr));
         src = dst;
       }
       for (int p = 0; p < passes; ++p) {
@@ -237,17 +234,13 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
       }
       // One event ends the blur passes and starts the assignment.
       if (timed) PLAS_HIP(h, hipEventRecord(h->events[3 * i + 1], h->stream));
-      PLAS_HIP(h, plas::launch_assign(G, T, P, table, Sd, dp, storage, max_items, h->stream));
+      PLAS_HIP(h, plas::launch_assign(G, T, P, table, Sd, dp, storage, max_items, h->stream, &control));
       if (timed) PLAS_HIP(h, hipEventRecord(h->events[3 * i + 2], h->stream));
     }
     const int64_t first_slot = slots;
     slots += chunk;
-    // The control step of a chunk's last reorder runs at the start of the
-    // next chunk, so `k` read here may lag the queued reorders by one.
-    PLAS_HIP(h, hipMemcpyAsync(h->status_host, &states[cur].done, sizeof(int32_t), hipMemcpyDeviceToHost,
-                               h->stream));
-    PLAS_HIP(h, hipMemcpyAsync(&h->status_host->k, &states[cur].k, sizeof(int64_t), hipMemcpyDeviceToHost,
-                               h->stream));
+    PLAS_HIP(h, hipMemcpyAsync(h->status_host, &Sd->done, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    PLAS_HIP(h, hipMemcpyAsync(&h->status_host->k, &Sd->k, sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
     PLAS_HIP(h, hipStreamSynchronize(h->stream));
     const bool done = h->status_host->done != 0;
     const int64_t k_now = h->status_host->k;
@@ -264,17 +257,17 @@ int32_t plas_sort(plas_handle h, const void* features, int64_t n, int32_t d, int
       }
     }
     if (done) break;
-    // Every queued slot but the last has been controlled by now; if k falls
-    // short the device state is broken. Also stop at the bound on reorders
-    // that the stall test implies (energies strictly fall by at least 1/M per
+    // Every queued slot has run and been controlled by now; if k falls short
+    // the device state is broken. Also stop at the bound on reorders that
+    // the stall test implies (energies strictly fall by at least 1/M per
     // improvement, two stalls end a level).
-    if (k_now - k0 < slots - 1 || k_now > max_k)
+    if (k_now - k0 != slots || k_now > max_k)
       return fail(h, PLAS_ERR_HIP, "device controller made no progress");
   }
 
   PLAS_HIP(h, hipMemcpyAsync(perm_out, P, static_cast<size_t>(n) * sizeof(int32_t), hipMemcpyDeviceToDevice,
                              h->stream));
-  PLAS_HIP(h, hipMemcpyAsync(S, &states[cur], sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+  PLAS_HIP(h, hipMemcpyAsync(S, Sd, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
   PLAS_HIP(h, hipStreamSynchronize(h->stream));
   if (stats != nullptr) {
     stats->levels = S->levels_run;

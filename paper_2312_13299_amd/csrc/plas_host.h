@@ -56,7 +56,7 @@ struct plas_context {
   plas_host::DeviceBuffer range_part, range_out;   // range pass scratch and result
   plas_host::DeviceBuffer levels;                  // LevelInfo[levels]
   plas_host::DeviceBuffer trace;                   // plas_level_out[levels]
-  plas_host::DeviceBuffer state;                   // two DevStates of a sort (read one, write the other)
+  plas_host::DeviceBuffer state;                   // DevState of a sort
   plas_host::DeviceBuffer stage_state;             // DevState of a stage call
   plas_host::DeviceBuffer scratch;                 // u64 accumulators and flags
   plas_host::DeviceBuffer vad;                     // VAD partial sums and results
@@ -348,7 +348,7 @@ inline int32_t apply_checkpoint(plas_context* h, DevState* S, const plas_sort_ch
   S->energy_last = ck.energy_last;
   S->level_reorders = ck.level_reorders;
   S->level_moved = ck.level_moved;
-  S->pending = 0;
+  S->blocks_done = 0;
   S->ended = ck.done != 0;
   S->done = S->ended || (S->max_reorders > 0 && S->k >= S->max_reorders);
   const plas::Words4 keys = plas::draw(S->seed, plas::kDrawGrouping, static_cast<uint64_t>(S->k));

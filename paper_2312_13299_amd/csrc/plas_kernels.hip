@@ -234,28 +234,31 @@ __global__ __launch_bounds__(kBlock) void k_gather(const S* __restrict__ X, cons
 
 // ------------------------------------------------------------------- blur
 
-// The controller step of the previous reorder and the grouping table of the
-// next one, run by every block of a row pass before it blurs (defined with
-// the controller below). NT: threads per block.
-template <int NT>
-__device__ void step_body(const DevState* __restrict__ in, DevState* __restrict__ out,
-                          const LevelInfo* __restrict__ levels, plas_level_out* __restrict__ trace,
-                          int32_t* __restrict__ table, int64_t bid, int64_t nblocks, DevState& s_st);
-
-// The radius of a pass: after the step (step.in set), from the new state in
-// LDS; else from st, or the fixed radius when st is NULL. Returns false when
-// the sort has ended.
-template <int NT>
-__device__ __forceinline__ bool pass_radius(const StepArgs& step, const DevState* __restrict__ st, int radius,
-                                            int64_t bid, int64_t nblocks, DevState& s_st, int& r) {
-  if (step.in != nullptr) {
-    step_body<NT>(step.in, step.out, step.levels, step.trace, step.table, bid, nblocks, s_st);
-    r = s_st.r;
-    return !s_st.done;
-  }
+// The radius of a pass: st->r, or the fixed radius when st is NULL. Returns
+// false when the sort has ended (every kernel queued after the end returns
+// at once).
+__device__ __forceinline__ bool pass_radius(const DevState* __restrict__ st, int radius, int& r) {
   if (st != nullptr && st->done) return false;
   r = st != nullptr ? st->r : radius;
   return true;
+}
+
+// table[t] = pi(t) packed as (ly << 16) | lx, pi the grouping bijection of
+// a reorder over the beta^2 block-local cells, filled by all blocks of a
+// launch (NT threads each). The first row pass of a reorder runs it after
+// its lines, from the state's beta and keys.
+template <int NT>
+__device__ __forceinline__ void fill_group_table(int32_t* __restrict__ table, int beta, const uint64_t keys[4],
+                                                 int64_t bid, int64_t nblocks) {
+  const uint64_t cells = static_cast<uint64_t>(beta) * beta;
+  const Bijection f(cells, keys);
+  const uint64_t stride = static_cast<uint64_t>(nblocks) * NT;
+  for (uint64_t t = static_cast<uint64_t>(bid) * NT + threadIdx.x; t < cells; t += stride) {
+    const uint32_t v = static_cast<uint32_t>(f(t));
+    const uint32_t ly = v / static_cast<uint32_t>(beta);
+    const uint32_t lx = v - ly * static_cast<uint32_t>(beta);
+    table[t] = static_cast<int32_t>((ly << 16) | lx);
+  }
 }
 
 // Orders this wave's LDS writes before its later LDS reads (lanes of one
@@ -447,69 +450,22 @@ inline int64_t blur_reg_waves(int w) {
 template <int DP, typename S>
 __global__ __launch_bounds__(kBlock) void k_blur(const S* __restrict__ in, S* __restrict__ out,
                                                  int w, const DevState* __restrict__ st, int radius,
-                                                 int vertical, const float* __restrict__ inv, StepArgs step) {
-  __shared__ DevState s_st;
+                                                 int vertical, const float* __restrict__ inv,
+                                                 int32_t* __restrict__ table) {
   int r;
-  if (!pass_radius<kBlock>(step, st, radius, blockIdx.x, gridDim.x, s_st, r)) return;
+  if (!pass_radius(st, radius, r)) return;
   const int64_t wave = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) >> 6;
   blur_reg_lines<DP, S>(in, out, w, r, vertical, inv, wave, threadIdx.x & 63);
+  if (table != nullptr) fill_group_table<kBlock>(table, st->beta, st->keys, blockIdx.x, gridDim.x);
 }
 
-// Blur pass for 64-channel cells, staged through LDS. Same arithmetic as
-// k_blur (one running sum per line and channel, same operation order), with
-// the memory side reorganised. A per-position load of one channel per lane
-// keeps only one position of the 64 chains in flight per instruction, far
-// below what HBM needs. Here every lane loads 16 bytes (4 float32 or 8
-// bfloat16 channels) of one of kPos consecutive cells, so one instruction
-// fetches kPos whole positions of the wave's line. A chunk of kChunk
-// positions of the entering and of the leaving stream (8 KB each in either
-// storage) is copied raw into LDS, where lane = channel reads it back in
-// order; outputs return through LDS and leave as 16-byte stores.
-//
-// Loads are issued unconditionally, at addresses clamped into the line (a
-// clamped load fetches a value the sums never use), so a chunk's fetch is
-// straight-line code: the next chunk's loads are issued right after the
-// current chunk has been copied to LDS and are in flight while it is summed.
-constexpr int kStageSub = 32;  // positions summed per pass over LDS
-
-template <typename S>
-struct StagedShape {
-  static constexpr int kChannels = 16 / static_cast<int>(sizeof(S));  // channels per 16-byte load
-  static constexpr int kLanesPerCell = 64 / kChannels;
-  static constexpr int kPos = 64 / kLanesPerCell;  // positions per load instruction
-  static constexpr int kVec = 8;                   // loads per stream per chunk
-  static constexpr int kChunk = kVec * kPos;       // 32 (float32) or 64 (bfloat16) positions
-  static_assert(kChunk % kStageSub == 0 && kChunk <= 64, "chunk shape");
-};
-
-// LDS of one wave: 24 KB in either storage.
-template <typename S>
-struct StagedLds {
-  S enter[StagedShape<S>::kChunk][64];
-  S leave[StagedShape<S>::kChunk][64];
-  S out[StagedShape<S>::kChunk][64];
-};
-
-template <typename S>
-struct StagedRegs {
-  uint4 enter[StagedShape<S>::kVec];
-  uint4 leave[StagedShape<S>::kVec];
-  float mult;  // lane p < kChunk: float32(1/count) of the chunk's position p
-};
-
-// A wave walks 64 / DP lines side by side (DP = 64: one line). LDS row p
-// holds position p of all of them: element l * DP + c is channel c of line
-// l, and lane l * DP + c runs that chain. For the memory side, the row is cut
-// into 16-byte pieces; load lane (q, j) moves piece j of position q of each
-// group of kPos positions, and piece j belongs to line j / kPiecesPerCell.
 // Streaming (non-temporal) cache hints, measured on the 1024^2 float32 and
-// 1448^2 bfloat16 sorts. The blur's outputs and its leaving-stream loads
-// are not read again before they leave the cache, and the assignment reads
+// 1448^2 bfloat16 sorts. The blur's outputs are not read again before they
+// leave the cache, and the assignment reads
 // every cell of G and T once per reorder: with these hints dirty blur output
 // no longer competes with the assignment's random reads (assignment 127 ->
 // 102 us at 1024^2 float32, whole sort -6 %).
 constexpr bool kBlurStreamStores = true;
-constexpr bool kBlurStreamLeave = true;
 constexpr bool kAssignStreamLoads = true;
 
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
@@ -550,174 +506,312 @@ __device__ __forceinline__ Q load_quad(const Q* p) {
     return *p;
   }
 }
+
+// Blur pass for cells of at least 16 bytes, staged through LDS. Same
+// arithmetic as k_blur (one running sum per line and channel, same operation
+// order); the memory side is built on gfx950's direct global -> LDS loads.
+//
+// A wave walks 64 / DP lines side by side (DP = 64: one line). LDS row p holds
+// one position of all of them: element l * DP + c is channel c of line l, and
+// lane l * DP + c runs that chain. A load instruction fills kPos consecutive
+// rows (1 KB): load lane (q, j) moves the 16-byte piece j of position q, piece
+// j belonging to line j / kPiecesPerCell, and the data goes straight to LDS
+// without passing through registers, so several chunks can be in flight per
+// wave. Outputs are summed into LDS rows and leave as 16-byte stores with a
+// streaming hint.
+//
+// Chunks are kChunk positions aligned to multiples of kChunk (a row walk then
+// reads and writes whole aligned 4 KB blocks). The line is loaded chunk by
+// chunk into a ring of rows (row = position modulo the ring). Step e takes
+// chunk e: first its positions up to min(r, w - 1) go into the starting sum,
+// then, from step A = ceil(r / kChunk) on, the outputs x of chunk e - A (x + r
+// lies in chunk e or e - 1). While the ring also holds every leaving position
+// x - r - 1 still to come beside the chunks in flight, leaving values are read
+// back from it; otherwise the ring is split in two halves and a second stream
+// loads the leaving chunks (the same positions again) into the upper half.
+// Loads are issued at positions clamped into the line (a clamped load fetches
+// a value the sums never use), so every chunk is exactly kVec load
+// instructions.
+//
+// Waits. Vector memory operations of a wave complete in issue order, so
+// "chunk c has arrived" is "at most n operations are outstanding", n being the
+// number of loads and stores issued after chunk c's last load. Every step
+// issues, in this order, the stores of the chunk it summed and then the loads
+// of issue slot e + kDepth - 1 (entering chunk, then leaving chunk); n follows
+// from that schedule (ops_after). The loads are written as asm so that the
+// compiler does not add its own conservative wait (every load done) before
+// each LDS read; M0 (the LDS base of a load) is set in the same asm statement,
+// and no compiler-generated code of these kernels uses M0.
+template <typename S>
+struct RingShape {
+  static constexpr int kRowBytes = 64 * static_cast<int>(sizeof(S));  // one position of the wave's lines
+  static constexpr int kLanesPerRow = kRowBytes / 16;
+  static constexpr int kPos = 64 / kLanesPerRow;  // positions per load instruction: 4 (float32), 8 (bfloat16)
+  static constexpr int kChunk = 16;               // positions per chunk
+  static constexpr int kVec = kChunk / kPos;      // load instructions per chunk
+#ifndef PLAS_BLUR_DEPTH
+#define PLAS_BLUR_DEPTH 3
+#endif
+#ifndef PLAS_BLUR_EARLY
+#define PLAS_BLUR_EARLY 0
+#endif
+  static constexpr int kDepth = PLAS_BLUR_DEPTH;  // issue slots in flight, the one being summed included
+  static constexpr bool kEarly = PLAS_BLUR_EARLY;  // a step issues its loads before summing (else after)
+  static constexpr int kRingRows = 128;
+  static constexpr int kSlots = kRingRows / kChunk;
+  static constexpr int kHalfRows = kRingRows / 2;  // rows of each stream when the ring is split
+  static_assert(kRingRows % kChunk == 0 && (kRingRows & (kRingRows - 1)) == 0, "ring shape");
+  static_assert(kHalfRows / kChunk >= kDepth + (kEarly ? 1 : 0), "a split half holds the chunks in use and in flight");
+};
+
+// LDS of one wave: 36 KB (float32) or 18 KB (bfloat16).
+template <typename S>
+struct RingLds {
+  S ring[RingShape<S>::kRingRows][64];
+  S out[RingShape<S>::kChunk][64];
+};
+
+// Leaving values come from the entering ring when, at every step, the chunk
+// issued then does not overwrite a leaving position still to come: with A =
+// ceil(r / kChunk) chunks between a step's chunk and its outputs and
+// ceil((r + 1) / kChunk) between an output chunk and its leaving positions,
+// A + ceil((r + 1) / kChunk) <= kSlots + 1 - kDepth.
+template <typename S>
+__device__ __forceinline__ bool ring_leave(int r) {
+  using Sh = RingShape<S>;
+  const int a = (r + Sh::kChunk - 1) / Sh::kChunk;
+  const int b = (r + Sh::kChunk) / Sh::kChunk;
+  return a + b <= Sh::kSlots + (Sh::kEarly ? 0 : 1) - Sh::kDepth;
+}
+
+// One direct load: 16 bytes per lane from `src` to LDS byte address
+// m0 + 16 * lane. A preceding LDS read of the rows it overwrites must have
+// completed: lgkmcnt(0) first.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"  // M0 is named as clobbered on purpose
+__device__ __forceinline__ void dma16(const void* src, uint32_t m0) {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+               :
+               : "v"(src), "s"(m0)
+               : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+// s_waitcnt vmcnt(n) for a run-time n (rounded down, which only waits
+// longer).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  asm volatile("s_waitcnt vmcnt(%0)" : : "n"(N) : "memory");
+}
+__device__ __forceinline__ void wait_vm_dyn(int n) {
+  switch (n < 0 ? 0 : n) {
+    case 0: wait_vm<0>(); break;
+    case 1: wait_vm<1>(); break;
+    case 2: wait_vm<2>(); break;
+    case 3: wait_vm<3>(); break;
+    case 4: wait_vm<4>(); break;
+    case 5: wait_vm<5>(); break;
+    case 6: wait_vm<6>(); break;
+    case 7: wait_vm<7>(); break;
+    case 8: wait_vm<8>(); break;
+    case 9: wait_vm<9>(); break;
+    case 10: wait_vm<10>(); break;
+    case 11: wait_vm<11>(); break;
+    case 12: wait_vm<12>(); break;
+    case 13: wait_vm<13>(); break;
+    case 14: wait_vm<14>(); break;
+    case 15: wait_vm<15>(); break;
+    default: wait_vm<16>(); break;
+  }
+}
+
 template <typename S, int DP>
-struct StagedLine {
-  using Shape = StagedShape<S>;
-  static constexpr int kChunk = Shape::kChunk;
+struct RingLine {
+  using Sh = RingShape<S>;
+  static constexpr int kChunk = Sh::kChunk;
   static constexpr int kPiecesPerCell = DP * static_cast<int>(sizeof(S)) / 16;
   static_assert(kPiecesPerCell >= 1, "a cell must hold at least one 16-byte piece");
   const S* __restrict__ src;  // the pass's input grid
   S* __restrict__ dst;        // and output grid
-  const float* __restrict__ inv;
-  int64_t step;    // elements between consecutive positions of a line
-  int64_t ld_off;  // element offset of this lane's load piece at position 0
-  int64_t own_off; // element offset of this lane's chain at position 0
-  bool ld_ok;      // the load piece's line exists (else its loads are clamped and its stores skipped)
-  bool own_ok;     // this lane's chain line exists
-  int w, r, first_hi, n_init, n_chunks;
+  int64_t step;     // elements between consecutive positions of a line
+  int64_t ld_off;   // element offset of this lane's load piece at position 0
+  bool ld_ok;       // the load piece's line exists (else its loads are clamped and its stores skipped)
+  int w, r, first_hi;
+  int n_chunks;  // M: chunks of the line
+  int ahead;     // A = ceil(r / kChunk): step e sums the outputs of chunk e - A
+  int lag;       // the leaving chunk needed at step e is e - lag (split ring)
+  int n_steps;   // A + M
   int q, j, lane;
-  StagedLds<S>* lds;
+  bool split;        // the leaving values have their own stream (the ring's upper half)
+  int enter_mask;    // ring rows of the entering stream - 1
+  uint32_t ring_m0;  // LDS byte address of ring row 0 (the same for all lanes)
+  RingLds<S>* lds;
 
   __device__ __forceinline__ int clamp_pos(int t) const { return t < 0 ? 0 : (t > w - 1 ? w - 1 : t); }
 
-  __device__ __forceinline__ uint4 ld(int t) const {
-    return *reinterpret_cast<const uint4*>(src + ld_off + static_cast<int64_t>(t) * step);
-  }
-
-  // Chunks 0 .. n_init-1 cover positions 0 .. first_hi of the starting sum
-  // (entering stream only); chunk n_init + k covers output positions
-  // 1 + k*kChunk onwards.
-  __device__ __forceinline__ void fetch(int c, StagedRegs<S>& R) const {
-    const bool init = c < n_init;
-    const int base = init ? c * kChunk : 1 + (c - n_init) * kChunk;
-    if (!init && base - r - 1 >= 0 && base + kChunk - 1 + r <= w - 1) {
-      // Every entering and leaving position of the chunk lies in the line:
-      // walk both streams with one pointer step per load.
-      const S* pe = src + ld_off + static_cast<int64_t>(base + r + q) * step;
-      const S* pl = src + ld_off + static_cast<int64_t>(base - r - 1 + q) * step;
-      const int64_t inc = static_cast<int64_t>(Shape::kPos) * step;
+  // kVec loads of chunk m (positions kChunk m ..) into rows row0 ..
+  __device__ __forceinline__ void load_chunk(int m, int row0) const {
+    const int pos0 = m * kChunk;
+    const uint32_t m0 = ring_m0 + static_cast<uint32_t>(row0 * Sh::kRowBytes);
+    if (pos0 + kChunk - 1 <= w - 1) {
+      const S* p = src + ld_off + static_cast<int64_t>(pos0 + q) * step;
+      const int64_t inc = static_cast<int64_t>(Sh::kPos) * step;
 #pragma unroll
-      for (int i = 0; i < Shape::kVec; ++i) {
-        R.enter[i] = *reinterpret_cast<const uint4*>(pe + i * inc);
-        R.leave[i] = load16<kBlurStreamLeave>(pl + i * inc);
-      }
+      for (int i = 0; i < Sh::kVec; ++i) dma16(p + i * inc, m0 + i * 1024u);
     } else {
 #pragma unroll
-      for (int i = 0; i < Shape::kVec; ++i) {
-        const int x = base + Shape::kPos * i + q;
-        const int a = init ? x : x + r;
-        const int b = init ? x : x - r - 1;
-        R.enter[i] = ld(clamp_pos(a));
-        R.leave[i] = ld(clamp_pos(b));
-      }
+      for (int i = 0; i < Sh::kVec; ++i)
+        dma16(src + ld_off + static_cast<int64_t>(clamp_pos(pos0 + Sh::kPos * i + q)) * step, m0 + i * 1024u);
     }
-    // Output chunks: lane p's multiplier is that of position base + p;
-    // starting chunks: that of position 0 (window 0 .. first_hi).
-    const int x = clamp_pos(base + (lane & (kChunk - 1)));
-    const int hi = x + r < w - 1 ? x + r : w - 1;
-    const int lo = x - r > 0 ? x - r : 0;
-    R.mult = inv[init ? first_hi + 1 : hi - lo + 1];
   }
 
-  __device__ __forceinline__ void stage(const StagedRegs<S>& R) const {
+  // Issue slot u: entering chunk u and, when split, leaving chunk u - lag.
+  __device__ __forceinline__ bool slot_enter(int u) const { return u < n_chunks; }
+  __device__ __forceinline__ bool slot_leave(int u) const { return split && u - lag >= 0 && u - lag < n_chunks; }
+  __device__ __forceinline__ void issue(int u) const {
+    if (slot_enter(u)) load_chunk(u, (u * kChunk) & enter_mask);
+    if (slot_leave(u)) load_chunk(u - lag, Sh::kHalfRows + (((u - lag) * kChunk) & (Sh::kHalfRows - 1)));
+  }
+  __device__ __forceinline__ int slot_loads(int u) const {
+    return Sh::kVec * ((slot_enter(u) ? 1 : 0) + (slot_leave(u) ? 1 : 0));
+  }
+  // Stores of step s: a whole output chunk (every output chunk but the last
+  // lies inside the line, and only the last step stores the last one).
+  __device__ __forceinline__ int step_stores(int s) const { return s >= ahead ? Sh::kVec : 0; }
+  // Operations issued after slot e's loads, as of the start of step e: the
+  // loads of slots e + 1 .. e + kDepth - 2 and the stores of the steps that
+  // came after slot e was issued.
+  __device__ __forceinline__ int ops_after(int e) const {
+    int n = 0;
 #pragma unroll
-    for (int i = 0; i < Shape::kVec; ++i) {
-      *reinterpret_cast<uint4*>(&lds->enter[Shape::kPos * i + q][Shape::kChannels * j]) = R.enter[i];
-      *reinterpret_cast<uint4*>(&lds->leave[Shape::kPos * i + q][Shape::kChannels * j]) = R.leave[i];
-    }
+    for (int u = 1; u <= Sh::kDepth - 2; ++u) n += slot_loads(e + u);
+    const int first = e - Sh::kDepth + (Sh::kEarly ? 1 : 2);
+    const int s0 = first > 0 ? first : 0;
+    for (int s = s0; s < e; ++s) n += step_stores(s);
+    return n;
   }
 
-  // Output positions x0 .. x0 + kStageSub - 1 (LDS rows p0 ..), all inside
-  // the grid, all with (ENTER) or without an entering value and all with
-  // (LEAVE) or without a leaving one: no per-position tests.
-  // With both an entering and a leaving value at every position the window
-  // holds 2r + 1 cells, and with neither it is the whole line: one
-  // multiplier serves all positions (the same table entry the per-position
-  // lookup would give). Otherwise each position takes its own from lane p.
+  __device__ __forceinline__ float enter_val(int x) const {
+    return Storage<S>::widen(lds->ring[(x + r) & enter_mask][lane]);
+  }
+  __device__ __forceinline__ float leave_val(int x) const {
+    const int t = x - r - 1;
+    const int row = split ? Sh::kHalfRows + (t & (Sh::kHalfRows - 1)) : (t & (Sh::kRingRows - 1));
+    return Storage<S>::widen(lds->ring[row][lane]);
+  }
+
+  // Outputs x0 .. x0 + kChunk - 1, all inside the grid, all with (ENTER) or
+  // without an entering value and all with (LEAVE) or without a leaving one:
+  // no per-position tests. With both at every position the window holds
+  // 2r + 1 cells, and with neither it is the whole line: one multiplier
+  // serves all positions. Otherwise each position takes its own from lane p.
   template <bool ENTER, bool LEAVE>
-  __device__ __forceinline__ void run_uniform(int p0, int mult_bits, float& s) const {
+  __device__ __forceinline__ void run_uniform(int x0, float mult, float& s) const {
     constexpr bool kConstMult = ENTER == LEAVE;
-    float e[kStageSub], l[kStageSub];
+    const int mult_bits = __float_as_int(mult);
+    float e[kChunk], l[kChunk];
 #pragma unroll
-    for (int p = 0; p < kStageSub; ++p) {
-      if (ENTER) e[p] = Storage<S>::widen(lds->enter[p0 + p][lane]);
-      if (LEAVE) l[p] = Storage<S>::widen(lds->leave[p0 + p][lane]);
+    for (int p = 0; p < kChunk; ++p) {
+      if (ENTER) e[p] = enter_val(x0 + p);
+      if (LEAVE) l[p] = leave_val(x0 + p);
     }
-    const float m_const = kConstMult ? __int_as_float(__builtin_amdgcn_readlane(mult_bits, p0)) : 0.0f;
+    const float m_const = kConstMult ? __int_as_float(__builtin_amdgcn_readfirstlane(mult_bits)) : 0.0f;
 #pragma unroll
-    for (int p = 0; p < kStageSub; ++p) {
+    for (int p = 0; p < kChunk; ++p) {
       if (ENTER) s = s + e[p];
       if (LEAVE) s = s - l[p];
-      const float m = kConstMult ? m_const : __int_as_float(__builtin_amdgcn_readlane(mult_bits, p0 + p));
-      lds->out[p0 + p][lane] = Storage<S>::narrow(s * m);
+      const float m = kConstMult ? m_const : __int_as_float(__builtin_amdgcn_readlane(mult_bits, p));
+      lds->out[p][lane] = Storage<S>::narrow(s * m);
     }
   }
 
-  // Any positions: the tests of each position select the update.
-  __device__ __forceinline__ void run_mixed(int x0, int p0, int mult_bits, float& s) const {
-    float e[kStageSub], l[kStageSub];
+  // Any outputs (x = 0 included: the starting sum as it is): the tests of
+  // each position select the update.
+  __device__ __forceinline__ void run_mixed(int x0, float mult, float& s) const {
+    const int mult_bits = __float_as_int(mult);
+    float e[kChunk], l[kChunk];
 #pragma unroll
-    for (int p = 0; p < kStageSub; ++p) {
-      e[p] = Storage<S>::widen(lds->enter[p0 + p][lane]);
-      l[p] = Storage<S>::widen(lds->leave[p0 + p][lane]);
+    for (int p = 0; p < kChunk; ++p) {
+      e[p] = enter_val(x0 + p);
+      l[p] = leave_val(x0 + p);
     }
 #pragma unroll
-    for (int p = 0; p < kStageSub; ++p) {
+    for (int p = 0; p < kChunk; ++p) {
       const int x = x0 + p;
-      const bool inside = x < w;
+      const bool inside = x >= 1 && x < w;
       const float with_enter = s + e[p];
       s = (inside && x + r <= w - 1) ? with_enter : s;
       const float with_leave = s - l[p];
       s = (inside && x - r - 1 >= 0) ? with_leave : s;
-      lds->out[p0 + p][lane] =
-          Storage<S>::narrow(s * __int_as_float(__builtin_amdgcn_readlane(mult_bits, p0 + p)));
+      lds->out[p][lane] = Storage<S>::narrow(s * __int_as_float(__builtin_amdgcn_readlane(mult_bits, p)));
     }
   }
 
-  // Sum chunk c from LDS and store its outputs. DS instructions of one wave
-  // execute in issue order, and every LDS read below may alias an earlier
-  // LDS write in the compiler's view, so program order suffices.
-  __device__ __forceinline__ void consume(int c, int mult_bits, float& s) const {
-    if (c < n_init) {
+  // The positions of chunk e up to first_hi, in ascending order, into the
+  // starting sum (position 0 starts it).
+  __device__ __forceinline__ void start_sum(int e, float& s) const {
+    const int t0 = e * kChunk;
+    float v[kChunk];
 #pragma unroll
-      for (int p0 = 0; p0 < kChunk; p0 += kStageSub) {
-        const int t0 = c * kChunk + p0;
-        float e[kStageSub];
+    for (int p = 0; p < kChunk; ++p) v[p] = Storage<S>::widen(lds->ring[(t0 + p) & enter_mask][lane]);
+    if (t0 > 0 && t0 + kChunk - 1 <= first_hi) {
 #pragma unroll
-        for (int p = 0; p < kStageSub; ++p) e[p] = Storage<S>::widen(lds->enter[p0 + p][lane]);
-        if (t0 > 0 && t0 + kStageSub - 1 <= first_hi) {
+      for (int p = 0; p < kChunk; ++p) s = s + v[p];
+    } else {
 #pragma unroll
-          for (int p = 0; p < kStageSub; ++p) s = s + e[p];
-        } else {
-#pragma unroll
-          for (int p = 0; p < kStageSub; ++p) {
-            const int t = t0 + p;
-            const float added = t == 0 ? e[p] : s + e[p];
-            s = t <= first_hi ? added : s;
-          }
-        }
+      for (int p = 0; p < kChunk; ++p) {
+        const int t = t0 + p;
+        const float added = t == 0 ? v[p] : s + v[p];
+        s = t <= first_hi ? added : s;
       }
-      if (c == n_init - 1 && own_ok)
-        dst[own_off] = Storage<S>::narrow(s * __int_as_float(__builtin_amdgcn_readfirstlane(mult_bits)));
-      return;
     }
-    const int x0c = 1 + (c - n_init) * kChunk;
-#pragma unroll
-    for (int p0 = 0; p0 < kChunk; p0 += kStageSub) {
-      const int x0 = x0c + p0;
-      const int x1 = x0 + kStageSub - 1;
-      // Position x has an entering value iff x + r <= w - 1 and a leaving
-      // value iff x - r - 1 >= 0.
-      const bool all_in = x1 < w;
-      const bool enter_all = x1 + r <= w - 1, enter_none = x0 + r > w - 1;
-      const bool leave_all = x0 - r - 1 >= 0, leave_none = x1 - r - 1 < 0;
-      if (all_in && enter_all && leave_all)
-        run_uniform<true, true>(p0, mult_bits, s);
-      else if (all_in && enter_all && leave_none)
-        run_uniform<true, false>(p0, mult_bits, s);
-      else if (all_in && enter_none && leave_all)
-        run_uniform<false, true>(p0, mult_bits, s);
-      else if (all_in && enter_none && leave_none)
-        run_uniform<false, false>(p0, mult_bits, s);
-      else
-        run_mixed(x0, p0, mult_bits, s);
+  }
+
+  // Output chunk k (positions x0 = k kChunk ..): sum, then store the chunk's
+  // rows as 16-byte pieces.
+  __device__ __forceinline__ void outputs(int k, float& s) const {
+    const int x0 = k * kChunk;
+    const int x1 = x0 + kChunk - 1;
+    // Lane p < kChunk: float32(1 / count) of position x0 + p (correctly
+    // rounded, as the host table 1.0f / c).
+    float mult;
+    {
+      const int x = clamp_pos(x0 + (lane & (kChunk - 1)));
+      const int hi = x + r < w - 1 ? x + r : w - 1;
+      const int lo = x - r > 0 ? x - r : 0;
+      mult = 1.0f / static_cast<float>(hi - lo + 1);
     }
+    const bool all_in = x0 >= 1 && x1 < w;
+    const bool enter_all = x1 + r <= w - 1, enter_none = x0 + r > w - 1;
+    const bool leave_all = x0 - r - 1 >= 0, leave_none = x1 - r - 1 < 0;
+    if (all_in && enter_all && leave_all)
+      run_uniform<true, true>(x0, mult, s);
+    else if (all_in && enter_all && leave_none)
+      run_uniform<true, false>(x0, mult, s);
+    else if (all_in && enter_none && leave_all)
+      run_uniform<false, true>(x0, mult, s);
+    else if (all_in && enter_none && leave_none)
+      run_uniform<false, false>(x0, mult, s);
+    else
+      run_mixed(x0, mult, s);
 #pragma unroll
-    for (int i = 0; i < Shape::kVec; ++i) {
-      const int x = x0c + Shape::kPos * i + q;
+    for (int i = 0; i < Sh::kVec; ++i) {
+      const int x = x0 + Sh::kPos * i + q;
       if (x < w && ld_ok)
         store16<kBlurStreamStores>(dst + ld_off + static_cast<int64_t>(x) * step,
-                                         *reinterpret_cast<const uint4*>(&lds->out[Shape::kPos * i + q][Shape::kChannels * j]));
+                                   *reinterpret_cast<const uint4*>(&lds->out[Sh::kPos * i + q][16 / sizeof(S) * j]));
+    }
+  }
+
+  __device__ __forceinline__ void run() const {
+    for (int u = 0; u <= Sh::kDepth - 2; ++u) issue(u);
+    float s = 0.0f;
+    for (int e = 0; e < n_steps; ++e) {
+      if (slot_loads(e) > 0) wait_vm_dyn(ops_after(e));
+      if (Sh::kEarly) issue(e + Sh::kDepth - 1);
+      if (e * kChunk <= first_hi) start_sum(e, s);
+      if (e >= ahead) outputs(e - ahead, s);
+      if (!Sh::kEarly) issue(e + Sh::kDepth - 1);
     }
   }
 };
@@ -726,46 +820,44 @@ struct StagedLine {
 // by one wave.
 template <typename S, int DP>
 __device__ __forceinline__ void blur_staged_line(const S* __restrict__ in, S* __restrict__ out, int w, int r,
-                                                 int vertical, const float* __restrict__ inv, int64_t line0,
-                                                 int lane, StagedLds<S>* lds) {
-  using L_t = StagedLine<S, DP>;
+                                                 int vertical, int64_t line0, int lane, RingLds<S>* lds) {
+  using Sh = RingShape<S>;
+  using L_t = RingLine<S, DP>;
   L_t L;
   // Element offset of line l at position 0, and between positions.
   auto line_off = [&](int64_t l) { return vertical ? l * DP : l * w * DP; };
   L.src = in;
   L.dst = out;
-  L.inv = inv;
   L.step = vertical ? static_cast<int64_t>(w) * DP : DP;
   L.w = w;
   L.r = r;
-  L.q = lane / StagedShape<S>::kLanesPerCell;
-  L.j = lane % StagedShape<S>::kLanesPerCell;
+  L.q = lane / Sh::kLanesPerRow;
+  L.j = lane % Sh::kLanesPerRow;
   const int64_t ld_line = line0 + L.j / L_t::kPiecesPerCell;
   L.ld_ok = ld_line < w;
-  L.ld_off = line_off(L.ld_ok ? ld_line : w - 1) + (L.j % L_t::kPiecesPerCell) * StagedShape<S>::kChannels;
-  const int64_t own_line = line0 + lane / DP;
-  L.own_ok = own_line < w;
-  L.own_off = line_off(L.own_ok ? own_line : w - 1) + lane % DP;
+  L.ld_off = line_off(L.ld_ok ? ld_line : w - 1) + (L.j % L_t::kPiecesPerCell) * (16 / static_cast<int>(sizeof(S)));
   L.lane = lane;
   L.lds = lds;
   if (r == 0) {
-    if (L.own_ok)
-      for (int x = 0; x < w; ++x) L.dst[L.own_off + x * L.step] = L.src[L.own_off + x * L.step];
+    const int64_t own_line = line0 + lane / DP;
+    const int64_t own_off = line_off(own_line < w ? own_line : w - 1) + lane % DP;
+    if (own_line < w)
+      for (int x = 0; x < w; ++x) L.dst[own_off + x * L.step] = L.src[own_off + x * L.step];
     return;
   }
-  constexpr int kChunk = StagedShape<S>::kChunk;
   L.first_hi = r < w - 1 ? r : w - 1;
-  L.n_init = (L.first_hi + kChunk) / kChunk;
-  L.n_chunks = L.n_init + (w - 1 + kChunk - 1) / kChunk;
-  float s = 0.0f;
-  StagedRegs<S> R;
-  L.fetch(0, R);
-  for (int c = 0; c < L.n_chunks; ++c) {
-    L.stage(R);
-    const int mult_bits = __float_as_int(R.mult);
-    if (c + 1 < L.n_chunks) L.fetch(c + 1, R);
-    L.consume(c, mult_bits, s);
-  }
+  L.n_chunks = (w + Sh::kChunk - 1) / Sh::kChunk;
+  L.ahead = (r + Sh::kChunk - 1) / Sh::kChunk;
+  L.n_steps = L.ahead + L.n_chunks;
+  L.split = !ring_leave<S>(r);
+  // Step e sums outputs of chunk k = e - A, whose leaving positions reach
+  // up to k kChunk + kChunk - 2 - r: chunk e - lag.
+  L.lag = L.ahead - ((Sh::kChunk - 2 - r) >= 0 ? (Sh::kChunk - 2 - r) / Sh::kChunk
+                                               : -((r - Sh::kChunk + 2 + Sh::kChunk - 1) / Sh::kChunk));
+  L.enter_mask = (L.split ? Sh::kHalfRows : Sh::kRingRows) - 1;
+  L.ring_m0 = __builtin_amdgcn_readfirstlane(
+      static_cast<uint32_t>(reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) S*)(&lds->ring[0][0]))));
+  L.run();
 }
 
 // One group of 64/DP lines per wave, WPB waves per block: block `bid` of
@@ -773,26 +865,24 @@ __device__ __forceinline__ void blur_staged_line(const S* __restrict__ in, S* __
 // there are more groups than waves.
 template <typename S, int DP, int WPB>
 __device__ __forceinline__ void blur_staged_lines(const S* __restrict__ in, S* __restrict__ out, int w, int r,
-                                                  int vertical, const float* __restrict__ inv, int64_t bid,
-                                                  int64_t nblocks, StagedLds<S>* stage) {
+                                                  int vertical, int64_t bid, int64_t nblocks, RingLds<S>* stage) {
   constexpr int kLinesPerWave = 64 / DP;
   const int wib = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   for (int64_t g = bid * WPB + wib; g * kLinesPerWave < w; g += nblocks * WPB)
-    blur_staged_line<S, DP>(in, out, w, r, vertical, inv, g * kLinesPerWave, lane, stage + wib);
+    blur_staged_line<S, DP>(in, out, w, r, vertical, g * kLinesPerWave, lane, stage + wib);
 }
 
 // Staged blur pass for cells of at least 16 bytes (DP * sizeof(S) >= 16).
 template <typename S, int DP, int WPB>
 __global__ __launch_bounds__(WPB * 64) void k_blur_staged(const S* __restrict__ in, S* __restrict__ out, int w,
                                                           const DevState* __restrict__ st, int radius,
-                                                          int vertical, const float* __restrict__ inv,
-                                                          StepArgs step) {
-  __shared__ StagedLds<S> s_stage[WPB];
-  __shared__ DevState s_st;
+                                                          int vertical, int32_t* __restrict__ table) {
+  __shared__ RingLds<S> s_stage[WPB];
   int r;
-  if (!pass_radius<WPB * 64>(step, st, radius, blockIdx.x, gridDim.x, s_st, r)) return;
-  blur_staged_lines<S, DP, WPB>(in, out, w, r, vertical, inv, blockIdx.x, gridDim.x, s_stage);
+  if (!pass_radius(st, radius, r)) return;
+  blur_staged_lines<S, DP, WPB>(in, out, w, r, vertical, blockIdx.x, gridDim.x, s_stage);
+  if (table != nullptr) fill_group_table<WPB * 64>(table, st->beta, st->keys, blockIdx.x, gridDim.x);
 }
 
 // Cells of DP * sizeof(S) bytes are moved in 16-byte pieces when they hold
@@ -810,26 +900,10 @@ inline int64_t staged_groups(int w) {
 
 // ---------------------------------------------------------- group table
 
-// table[t] = pi(t) packed as (ly << 16) | lx, pi the grouping bijection of
-// a reorder over the beta^2 block-local cells, filled by all blocks.
-template <int NT = kBlock>
-__device__ __forceinline__ void fill_group_table(int32_t* __restrict__ table, int beta, const uint64_t keys[4],
-                                                 int64_t bid, int64_t nblocks) {
-  const uint64_t cells = static_cast<uint64_t>(beta) * beta;
-  const Bijection f(cells, keys);
-  const uint64_t stride = static_cast<uint64_t>(nblocks) * NT;
-  for (uint64_t t = static_cast<uint64_t>(bid) * NT + threadIdx.x; t < cells; t += stride) {
-    const uint32_t v = static_cast<uint32_t>(f(t));
-    const uint32_t ly = v / static_cast<uint32_t>(beta);
-    const uint32_t lx = v - ly * static_cast<uint32_t>(beta);
-    table[t] = static_cast<int32_t>((ly << 16) | lx);
-  }
-}
-
 __global__ __launch_bounds__(kBlock) void k_group_table(int32_t* __restrict__ table,
                                                         const DevState* __restrict__ st) {
   if (st->done) return;
-  fill_group_table(table, st->beta, st->keys, blockIdx.x, gridDim.x);
+  fill_group_table<kBlock>(table, st->beta, st->keys, blockIdx.x, gridDim.x);
 }
 
 // Squared distance partial over one lane's 4 channels, as the two lowest
@@ -1194,10 +1268,22 @@ __device__ __forceinline__ void assign_items(S* __restrict__ G, const S* __restr
       m += s_sum[1][i];
     }
     const int slot_acc = static_cast<int>(bid % kAccSlots);
-    atomicAdd(&st->energy_acc[slot_acc], e);
-    atomicAdd(&st->moved_acc[slot_acc], m);
+    const unsigned long long e_old =
+        __hip_atomic_fetch_add(&st->energy_acc[slot_acc], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long m_old =
+        __hip_atomic_fetch_add(&st->moved_acc[slot_acc], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // Wait for both results: once they have returned, both additions have
+    // been made where every block's atomics meet, before anything this
+    // thread does next (the control step's ticket).
+    asm volatile("" : : "v"(e_old), "v"(m_old) : "memory");
   }
 }
+
+// The control step at the end of a reorder's assignment (defined with the
+// controller below).
+template <int NT>
+__device__ void reorder_done(DevState* __restrict__ st, const LevelInfo* __restrict__ levels,
+                             plas_level_out* __restrict__ trace, uint32_t nblocks);
 
 #ifndef PLAS_ASSIGN_WAVES_PER_EU
 #define PLAS_ASSIGN_WAVES_PER_EU 4
@@ -1216,12 +1302,12 @@ constexpr int assign_waves_per_eu() {
 
 template <int DP, typename S>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(assign_waves_per_eu<S, DP>())))
-void k_assign(S* __restrict__ G, const S* __restrict__ T,
-                                                   int32_t* __restrict__ P,
-                                                   const int32_t* __restrict__ table,
-                                                   DevState* __restrict__ st) {
+void k_assign(S* __restrict__ G, const S* __restrict__ T, int32_t* __restrict__ P,
+              const int32_t* __restrict__ table, DevState* __restrict__ st,
+              const LevelInfo* __restrict__ levels, plas_level_out* __restrict__ trace, int control) {
   if (st->done) return;
   assign_items<DP, S>(G, T, P, table, st, blockIdx.x, gridDim.x);
+  if (control) reorder_done<kBlock>(st, levels, trace, gridDim.x);
 }
 
 // ----------------------------------------------------------------- energy
@@ -1319,14 +1405,19 @@ __global__ __launch_bounds__(kBlock) void k_vad_finish(const double* __restrict_
 // E is compared with the previous energy; an improvement of at least
 // ceil(E_prev / M) keeps the level and its block shift; the first stall
 // draws a new shift; a stall right after a new shift ends the level
-// (phi <- decay * phi, precomputed in `levels`). trace may be NULL.
+// (phi <- decay * phi, precomputed in `levels`). `shift` is block shift
+// number st.j and `keys` the grouping keys of reorder st.k + 1, both drawn
+// beforehand (they do not depend on E). trace may be NULL.
 __device__ void control_step(DevState& st, const LevelInfo* __restrict__ levels,
-                             plas_level_out* __restrict__ trace) {
+                             plas_level_out* __restrict__ trace, const int32_t shift[2], const uint64_t keys[4]) {
   unsigned long long E = 0, moved = 0;
   for (int i = 0; i < kAccSlots; ++i) {
     E += st.energy_acc[i];
     moved += st.moved_acc[i];
+    st.energy_acc[i] = 0;
+    st.moved_acc[i] = 0;
   }
+  st.blocks_done = 0;
   st.k += 1;
   st.level_reorders += 1;
   st.level_moved += moved;
@@ -1363,7 +1454,8 @@ __device__ void control_step(DevState& st, const LevelInfo* __restrict__ levels,
       st.groups_per_block = lv.groups_per_block;
       st.groups = lv.groups;
       st.singles = lv.singles;
-      block_shift(st.seed, st.j, st.w, &st.dy, &st.dx);
+      st.dy = shift[0];
+      st.dx = shift[1];
       st.j += 1;
       st.has_prev = 0;
       st.just_shifted = 0;
@@ -1371,46 +1463,59 @@ __device__ void control_step(DevState& st, const LevelInfo* __restrict__ levels,
       st.level_moved = 0;
     }
   } else {
-    block_shift(st.seed, st.j, st.w, &st.dy, &st.dx);
+    st.dy = shift[0];
+    st.dx = shift[1];
     st.j += 1;
     st.just_shifted = 1;
     st.energy_prev = E;
   }
   if (st.max_reorders > 0 && st.k >= st.max_reorders) st.done = 1;
-  if (!st.done) {
-    const Words4 keys = draw(st.seed, kDrawGrouping, static_cast<uint64_t>(st.k));
-    for (int i = 0; i < 4; ++i) st.keys[i] = keys.v[i];
-  }
+  if (!st.done)
+    for (int i = 0; i < 4; ++i) st.keys[i] = keys[i];
 }
 
-// Between reorders: the control step of the reorder that just ran and the
-// grouping table of the next one, run at the start of the next reorder's
-// row pass. The state is double-buffered: every block reads `in` (nothing
-// writes it during this launch) and applies the same control step to its
-// own LDS copy, so all blocks agree on the next radius, beta and keys; block
-// 0 alone writes `out` and the trace; the blocks fill the table together.
+// The end of a reorder's assignment launch, run by every block after it has
+// added its sums to the state (NT threads per block, nblocks blocks of this
+// sort). Each block takes a ticket (an atomic increment, made after its sums
+// have been added); the one that draws the last ticket sees every block's
+// sums and runs the control step on the state in place: no block of the
+// launch reads the state after taking its ticket, and the next launch of the
+// sort starts after this one ends. Device-scope fences are not needed and
+// would be costly here (each writes back the L2 of its chiplet): the sums,
+// the tickets and the last block's reads are all device-scope atomics. The
+// two random draws the step may use run at the same time on two other
+// waves.
 template <int NT>
-__device__ void step_body(const DevState* __restrict__ in, DevState* __restrict__ out,
-                          const LevelInfo* __restrict__ levels, plas_level_out* __restrict__ trace,
-                          int32_t* __restrict__ table, int64_t bid, int64_t nblocks, DevState& s_st) {
+__device__ void reorder_done(DevState* __restrict__ st, const LevelInfo* __restrict__ levels,
+                             plas_level_out* __restrict__ trace, uint32_t nblocks) {
+  static_assert(NT >= 192, "the draws run on the second and third waves");
   static_assert(sizeof(DevState) % 4 == 0, "state is copied as 32-bit words");
   constexpr int kWords = sizeof(DevState) / 4;
-  uint32_t* words = reinterpret_cast<uint32_t*>(&s_st);
-  for (int i = threadIdx.x; i < kWords; i += NT) words[i] = reinterpret_cast<const uint32_t*>(in)[i];
+  __shared__ DevState s_st;
+  __shared__ uint32_t s_last;
+  __shared__ int32_t s_shift[2];
+  __shared__ uint64_t s_keys[4];
+  if (threadIdx.x == 0)
+    s_last = __hip_atomic_fetch_add(&st->blocks_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nblocks - 1
+                 ? 1u
+                 : 0u;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    if (!s_st.done && s_st.pending) control_step(s_st, levels, bid == 0 ? trace : nullptr);
-    s_st.pending = 1;
-    for (int i = 0; i < kAccSlots; ++i) {
-      s_st.energy_acc[i] = 0;
-      s_st.moved_acc[i] = 0;
-    }
+  if (s_last == 0) return;
+  uint32_t* words = reinterpret_cast<uint32_t*>(&s_st);
+  uint32_t* gwords = reinterpret_cast<uint32_t*>(st);
+  for (int i = threadIdx.x; i < kWords; i += NT)
+    words[i] = __hip_atomic_load(gwords + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (threadIdx.x == 64) {
+    block_shift(s_st.seed, s_st.j, s_st.w, &s_shift[0], &s_shift[1]);
+  } else if (threadIdx.x == 128) {
+    const Words4 k = draw(s_st.seed, kDrawGrouping, static_cast<uint64_t>(s_st.k + 1));
+    for (int i = 0; i < 4; ++i) s_keys[i] = k.v[i];
   }
   __syncthreads();
-  if (bid == 0)
-    for (int i = threadIdx.x; i < kWords; i += NT) reinterpret_cast<uint32_t*>(out)[i] = words[i];
-  if (s_st.done) return;
-  fill_group_table<NT>(table, s_st.beta, s_st.keys, bid, nblocks);
+  if (threadIdx.x == 0) control_step(s_st, levels, trace, s_shift, s_keys);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kWords; i += NT) gwords[i] = words[i];
 }
 
 // ------------------------------------------------------------------ batch
@@ -1435,7 +1540,7 @@ struct BatchGridView {
   const float PLAS_GLOBAL* inv;
   const LevelInfo PLAS_GLOBAL* levels;
   plas_level_out PLAS_GLOBAL* trace;
-  DevState PLAS_GLOBAL* states;
+  DevState PLAS_GLOBAL* state;
   int32_t w;
   int32_t blur_blocks;
   int32_t assign_blocks;
@@ -1458,24 +1563,11 @@ __device__ __forceinline__ T* global_ptr(U PLAS_GLOBAL* p) {
   return (T*)((T PLAS_GLOBAL*)p);
 }
 
-// The first row pass of a reorder first steps the sort's controller from
-// state state_idx ^ 1 to state_idx (the one the reorder then uses).
-__device__ __forceinline__ StepArgs batch_step(const BatchGridView& g, int state_idx, bool with_step) {
-  StepArgs a{};  // table_cells is a host-side launch-size hint, unused here
-  if (!with_step) return a;
-  DevState* states = global_ptr<DevState>(g.states);
-  a.in = states + (state_idx ^ 1);
-  a.out = states + state_idx;
-  a.levels = global_ptr<const LevelInfo>(g.levels);
-  a.trace = global_ptr<plas_level_out>(g.trace);
-  a.table = global_ptr<int32_t>(g.table);
-  return a;
-}
-
 // A batch blur pass's route (see launch_blur_batch): its axis, source and
-// destination grids (0 G, 1 H, 2 T) and whether it runs the step.
+// destination grids (0 G, 1 H, 2 T) and whether it fills the grouping table
+// afterwards (the first row pass of a reorder).
 __device__ __forceinline__ int route_vertical(int route) { return route & 1; }
-__device__ __forceinline__ bool route_step(int route) { return (route >> 5) & 1; }
+__device__ __forceinline__ bool route_table(int route) { return (route >> 5) & 1; }
 template <typename S>
 __device__ __forceinline__ S* route_grid(const BatchGridView& g, int sel) {
   return global_ptr<S>(sel == 0 ? g.G : sel == 1 ? g.H : g.T);
@@ -1483,62 +1575,61 @@ __device__ __forceinline__ S* route_grid(const BatchGridView& g, int sel) {
 
 template <typename S, int DP, int WPB>
 __global__ __launch_bounds__(WPB * 64) void k_blur_staged_batch(const BatchGrid* __restrict__ grids,
-                                                                const uint32_t* __restrict__ map,
-                                                                int state_idx, int route) {
-  __shared__ StagedLds<S> s_stage[WPB];
-  __shared__ DevState s_st;
+                                                                const uint32_t* __restrict__ map, int route) {
+  __shared__ RingLds<S> s_stage[WPB];
   uint32_t local;
   const BatchGridView& g = batch_grid(grids, map, local);
+  const DevState* st = global_ptr<const DevState>(g.state);
   int r;
-  if (!pass_radius<WPB * 64>(batch_step(g, state_idx, route_step(route)),
-                             global_ptr<const DevState>(g.states) + state_idx, 0, local, g.blur_blocks, s_st, r))
-    return;
+  if (!pass_radius(st, 0, r)) return;
   const int vertical = route_vertical(route);
   const S* in = route_grid<S>(g, (route >> 1) & 3);
   S* out = route_grid<S>(g, (route >> 3) & 3);
-  blur_staged_lines<S, DP, WPB>(in, out, g.w, r, vertical, global_ptr<const float>(g.inv), local, g.blur_blocks,
-                                s_stage);
+  blur_staged_lines<S, DP, WPB>(in, out, g.w, r, vertical, local, g.blur_blocks, s_stage);
+  if (route_table(route))
+    fill_group_table<WPB * 64>(global_ptr<int32_t>(g.table), st->beta, st->keys, local, g.blur_blocks);
 }
 
 template <int DP, typename S>
 __global__ __launch_bounds__(kBlock) void k_blur_batch(const BatchGrid* __restrict__ grids,
-                                                       const uint32_t* __restrict__ map, int state_idx,
-                                                       int route) {
-  __shared__ DevState s_st;
+                                                       const uint32_t* __restrict__ map, int route) {
   uint32_t local;
   const BatchGridView& g = batch_grid(grids, map, local);
+  const DevState* st = global_ptr<const DevState>(g.state);
   int r;
-  if (!pass_radius<kBlock>(batch_step(g, state_idx, route_step(route)),
-                           global_ptr<const DevState>(g.states) + state_idx, 0, local, g.blur_blocks, s_st, r))
-    return;
+  if (!pass_radius(st, 0, r)) return;
   const int vertical = route_vertical(route);
   const S* in = route_grid<S>(g, (route >> 1) & 3);
   S* out = route_grid<S>(g, (route >> 3) & 3);
   const int64_t wave = (static_cast<int64_t>(local) * kBlock + threadIdx.x) >> 6;
   blur_reg_lines<DP, S>(in, out, g.w, r, vertical, global_ptr<const float>(g.inv), wave, threadIdx.x & 63);
+  if (route_table(route))
+    fill_group_table<kBlock>(global_ptr<int32_t>(g.table), st->beta, st->keys, local, g.blur_blocks);
 }
 
+// Every block of a sort adds its sums; the last one of the sort runs its
+// control step.
 template <int DP, typename S>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(assign_waves_per_eu<S, DP>())))
-void k_assign_batch(const BatchGrid* __restrict__ grids,
-                                                         const uint32_t* __restrict__ map, int state_idx) {
+void k_assign_batch(const BatchGrid* __restrict__ grids, const uint32_t* __restrict__ map) {
   uint32_t local;
   const BatchGridView& g = batch_grid(grids, map, local);
-  DevState* st = global_ptr<DevState>(g.states) + state_idx;
+  DevState* st = global_ptr<DevState>(g.state);
   if (st->done) return;
   assign_items<DP, S>(global_ptr<S>(g.G), global_ptr<const S>(g.T), global_ptr<int32_t>(g.P),
                       global_ptr<const int32_t>(g.table), st, local, g.assign_blocks);
+  reorder_done<kBlock>(st, global_ptr<const LevelInfo>(g.levels), global_ptr<plas_level_out>(g.trace),
+                       static_cast<uint32_t>(g.assign_blocks));
 }
 
-// (done, k) of each listed sort's state `state_idx`, for the host's check
-// between chunks.
+// (done, k) of each listed sort's state, for the host's check between
+// chunks.
 __global__ __launch_bounds__(kBlock) void k_batch_status(const BatchGrid* __restrict__ grids,
                                                          const int32_t* __restrict__ list, int count,
-                                                         int state_idx, HostStatus* __restrict__ out) {
+                                                         HostStatus* __restrict__ out) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= count) return;
-  const DevState* st =
-      global_ptr<const DevState>(reinterpret_cast<const BatchGridView*>(grids)[list[i]].states) + state_idx;
+  const DevState* st = global_ptr<const DevState>(reinterpret_cast<const BatchGridView*>(grids)[list[i]].state);
   HostStatus hs;
   hs.done = st->done;
   hs.pad = 0;
@@ -1641,32 +1732,32 @@ hipError_t launch_gather(const void* X, const int32_t* P, void* G, int64_t n, in
 // hold whole 16-byte pieces, else the register kernel.
 template <typename S, int DP>
 hipError_t blur_pass_dp(const void* in, void* out, int w, const DevState* st, int radius, int vertical,
-                        const float* inv, hipStream_t stream, const StepArgs& sa) {
-  // With the step, also enough blocks to fill the grouping table at about
-  // one entry per thread (blocks beyond the lines only do that).
+                        const float* inv, hipStream_t stream, const TableArgs& ta) {
+  // With the table, also enough blocks to fill it at about one entry per
+  // thread (blocks beyond the lines only do that).
   auto with_table = [&](int64_t blocks, int threads) {
-    if (sa.in == nullptr) return static_cast<int>(blocks);
-    const int64_t need = std::min<int64_t>(1024, (sa.table_cells + threads - 1) / threads);
+    if (ta.table == nullptr) return static_cast<int>(blocks);
+    const int64_t need = std::min<int64_t>(1024, (ta.max_cells + threads - 1) / threads);
     return static_cast<int>(std::max<int64_t>(blocks, need));
   };
   if constexpr (staged_cells<S, DP>()) {
     constexpr int kThreads = kBlurWavesPerBlock * 64;
     const int blocks = with_table((staged_groups<DP>(w) + kBlurWavesPerBlock - 1) / kBlurWavesPerBlock, kThreads);
     k_blur_staged<S, DP, kBlurWavesPerBlock><<<blocks, kThreads, 0, stream>>>(
-        static_cast<const S*>(in), static_cast<S*>(out), w, st, radius, vertical, inv, sa);
+        static_cast<const S*>(in), static_cast<S*>(out), w, st, radius, vertical, ta.table);
   } else {
     const int blocks = with_table((blur_reg_waves<DP>(w) + kWavesPerBlock - 1) / kWavesPerBlock, kBlock);
     k_blur<DP, S><<<blocks, kBlock, 0, stream>>>(static_cast<const S*>(in), static_cast<S*>(out), w, st, radius,
-                                                 vertical, inv, sa);
+                                                 vertical, inv, ta.table);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_blur_pass(const void* in, void* out, int w, int dp, int storage, const DevState* st,
-                            int radius, int vertical, const float* inv, hipStream_t stream, const StepArgs* step) {
-  const StepArgs sa = step != nullptr ? *step : StepArgs{};
+                            int radius, int vertical, const float* inv, hipStream_t stream, const TableArgs* table) {
+  const TableArgs ta = table != nullptr ? *table : TableArgs{};
   PLAS_DISPATCH_STORAGE(storage, {
-    PLAS_DISPATCH_DP(dp, return (blur_pass_dp<SV, DPV>(in, out, w, st, radius, vertical, inv, stream, sa)));
+    PLAS_DISPATCH_DP(dp, return (blur_pass_dp<SV, DPV>(in, out, w, st, radius, vertical, inv, stream, ta)));
   });
   return hipSuccess;
 }
@@ -1685,13 +1776,16 @@ inline int64_t assign_items_per_wave(int dp, int storage) {
 }
 
 hipError_t launch_assign(void* G, const void* T, int32_t* P, const int32_t* table, DevState* st, int dp,
-                         int storage, int64_t max_items, hipStream_t stream) {
+                         int storage, int64_t max_items, hipStream_t stream, const ControlArgs* control) {
   const int64_t items_per_wave = assign_items_per_wave(dp, storage);
   const int64_t waves = (max_items + items_per_wave - 1) / items_per_wave;
   const int blocks = blocks_for(waves * 64, assign_blocks_cap(storage));
+  const ControlArgs ca = control != nullptr ? *control : ControlArgs{};
+  const int with_control = control != nullptr ? 1 : 0;
   PLAS_DISPATCH_STORAGE(storage, {
     PLAS_DISPATCH_DP(dp, (k_assign<DPV, SV><<<blocks, kBlock, 0, stream>>>(
-                             static_cast<SV*>(G), static_cast<const SV*>(T), P, table, st)));
+                             static_cast<SV*>(G), static_cast<const SV*>(T), P, table, st, ca.levels, ca.trace,
+                             with_control)));
   });
   return hipGetLastError();
 }
@@ -1768,54 +1862,53 @@ int assign_blocks_cap(int storage) {
 
 template <typename S, int DP>
 hipError_t blur_batch_dp(const BatchGrid* grids, const uint32_t* map, int blocks, int waves_per_block,
-                         int state_idx, int route, hipStream_t stream) {
+                         int route, hipStream_t stream) {
   if constexpr (staged_cells<S, DP>()) {
     switch (waves_per_block) {
       case 1:
-        k_blur_staged_batch<S, DP, 1><<<blocks, 64, 0, stream>>>(grids, map, state_idx, route);
+        k_blur_staged_batch<S, DP, 1><<<blocks, 64, 0, stream>>>(grids, map, route);
         break;
       case 2:
-        k_blur_staged_batch<S, DP, 2><<<blocks, 128, 0, stream>>>(grids, map, state_idx, route);
+        k_blur_staged_batch<S, DP, 2><<<blocks, 128, 0, stream>>>(grids, map, route);
         break;
       case 4:
-        k_blur_staged_batch<S, DP, 4><<<blocks, 256, 0, stream>>>(grids, map, state_idx, route);
+        k_blur_staged_batch<S, DP, 4><<<blocks, 256, 0, stream>>>(grids, map, route);
         break;
       default:
         return hipErrorInvalidValue;
     }
   } else {
-    k_blur_batch<DP, S><<<blocks, kBlock, 0, stream>>>(grids, map, state_idx, route);
+    k_blur_batch<DP, S><<<blocks, kBlock, 0, stream>>>(grids, map, route);
   }
   return hipGetLastError();
 }
 
-int blur_route(int vertical, int src, int dst, int with_step) {
-  return (vertical & 1) | ((src & 3) << 1) | ((dst & 3) << 3) | ((with_step & 1) << 5);
+int blur_route(int vertical, int src, int dst, int with_table) {
+  return (vertical & 1) | ((src & 3) << 1) | ((dst & 3) << 3) | ((with_table & 1) << 5);
 }
 
 hipError_t launch_blur_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
-                             int waves_per_block, int state_idx, int route, hipStream_t stream) {
+                             int waves_per_block, int route, hipStream_t stream) {
   const int src = (route >> 1) & 3, dst = (route >> 3) & 3;
   if (src > 2 || dst < 1 || dst > 2 || src == dst) return hipErrorInvalidValue;
   PLAS_DISPATCH_STORAGE(storage, {
-    PLAS_DISPATCH_DP(dp, return (blur_batch_dp<SV, DPV>(grids, map, blocks, waves_per_block, state_idx, route,
-                                                        stream)));
+    PLAS_DISPATCH_DP(dp, return (blur_batch_dp<SV, DPV>(grids, map, blocks, waves_per_block, route, stream)));
   });
   return hipSuccess;
 }
 
 hipError_t launch_assign_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
-                               int state_idx, hipStream_t stream) {
+                               hipStream_t stream) {
   PLAS_DISPATCH_STORAGE(storage, {
-    PLAS_DISPATCH_DP(dp, (k_assign_batch<DPV, SV><<<blocks, kBlock, 0, stream>>>(grids, map, state_idx)));
+    PLAS_DISPATCH_DP(dp, (k_assign_batch<DPV, SV><<<blocks, kBlock, 0, stream>>>(grids, map)));
   });
   return hipGetLastError();
 }
 
-hipError_t launch_batch_status(const BatchGrid* grids, const int32_t* list, int count, int state_idx,
-                               HostStatus* out, hipStream_t stream) {
+hipError_t launch_batch_status(const BatchGrid* grids, const int32_t* list, int count, HostStatus* out,
+                               hipStream_t stream) {
   if (count <= 0) return hipSuccess;
-  k_batch_status<<<(count + kBlock - 1) / kBlock, kBlock, 0, stream>>>(grids, list, count, state_idx, out);
+  k_batch_status<<<(count + kBlock - 1) / kBlock, kBlock, 0, stream>>>(grids, list, count, out);
   return hipGetLastError();
 }
 

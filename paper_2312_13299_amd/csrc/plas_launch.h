@@ -43,32 +43,36 @@ hipError_t launch_check_perm(const int32_t* init, int64_t n, int32_t* counts, in
 // G[p] = X[P[p]] over dp channels (P NULL: identity).
 hipError_t launch_gather(const void* X, const int32_t* P, void* G, int64_t n, int dp, int storage,
                          hipStream_t stream);
-// The controller step a row pass runs first: the control step of the
-// reorder that ran on `in` (its energy, the stall test, the schedule),
-// written to `out` (a different state buffer), and the grouping table of the
-// coming reorder; the pass then blurs with `out`'s radius.
-struct StepArgs {
-  const DevState* in;
-  DevState* out;
-  const LevelInfo* levels;
-  plas_level_out* trace;
+// The grouping table a reorder's first row pass fills after its lines, from
+// the state's beta and keys.
+struct TableArgs {
   int32_t* table;
-  int64_t table_cells;  // largest beta^2 of the sort: the pass launches enough blocks to fill it quickly
+  int64_t max_cells;  // largest beta^2 of the sort: the pass launches enough blocks to fill it quickly
 };
 
-// One blur pass (vertical = 0: rows, 1: columns). Its radius: after the
-// step when step is given (rows), else st->r, or `radius` if st is NULL.
-// inv: float32 1/c for c = 0..w.
+// One blur pass (vertical = 0: rows, 1: columns) with radius st->r, or
+// `radius` if st is NULL (a pass queued after the end of the sort returns at
+// once). inv: float32 1/c for c = 0..w (the register kernel's multipliers).
 hipError_t launch_blur_pass(const void* in, void* out, int w, int dp, int storage, const DevState* st,
                             int radius, int vertical, const float* inv, hipStream_t stream,
-                            const StepArgs* step = nullptr);
+                            const TableArgs* table = nullptr);
 // Grouping table of the current reorder: table[t] = packed pi(t), t < beta^2.
 hipError_t launch_group_table(int32_t* table, const DevState* st, int64_t max_cells,
                               hipStream_t stream);
+// What the control step at the end of a sort's assignment needs: the level
+// table and the per-level trace (may be NULL).
+struct ControlArgs {
+  const LevelInfo* levels;
+  plas_level_out* trace;
+};
+
 // One blockwise assignment with the parameters in st. max_items bounds
-// groups + singles over every level this launch may see.
+// groups + singles over every level this launch may see. With `control`,
+// the last block to finish runs the control step of the reorder on st in
+// place (the energy and moved sums, the stall test, the schedule, the next
+// shift and grouping keys); without it, st keeps the sums for the caller.
 hipError_t launch_assign(void* G, const void* T, int32_t* P, const int32_t* table, DevState* st, int dp,
-                         int storage, int64_t max_items, hipStream_t stream);
+                         int storage, int64_t max_items, hipStream_t stream, const ControlArgs* control = nullptr);
 // VAD (App. C) of features[perm] on a w x w grid: out[0] receives the mean
 // |a - b| over neighbour pairs and channels, out[1] the variance. part:
 // device scratch of vad_partial_doubles() doubles; out: device double[2].
@@ -90,19 +94,20 @@ int batch_assign_blocks(int64_t max_items, int dp, int storage, int cap);  // ca
 int assign_blocks_cap(int storage);  // blocks of an assignment launch without a tuned value
 // A batch blur pass's route: its axis (vertical 0: rows, 1: columns), its
 // source and destination grids (0 G, 1 H, 2 T; the destination H or T, not
-// the source) and whether it first steps each grid's controller from
-// states[state_idx ^ 1] to states[state_idx] and fills its grouping table
-// (the first row pass of a reorder).
-int blur_route(int vertical, int src, int dst, int with_step);
+// the source) and whether it fills each grid's grouping table after its
+// lines (the first row pass of a reorder).
+int blur_route(int vertical, int src, int dst, int with_table);
 // One blur pass along `route` of every mapped grid, all of dp channels and
-// `storage`, with states[state_idx].
+// `storage`.
 hipError_t launch_blur_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
-                             int waves_per_block, int state_idx, int route, hipStream_t stream);
+                             int waves_per_block, int route, hipStream_t stream);
+// One assignment of every mapped grid; each grid's last block runs its
+// control step.
 hipError_t launch_assign_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
-                               int state_idx, hipStream_t stream);
-// out[i] = (done, k) of grids[list[i]].states[state_idx], i < count.
-hipError_t launch_batch_status(const BatchGrid* grids, const int32_t* list, int count, int state_idx,
-                               HostStatus* out, hipStream_t stream);
+                               hipStream_t stream);
+// out[i] = (done, k) of grids[list[i]]'s state, i < count.
+hipError_t launch_batch_status(const BatchGrid* grids, const int32_t* list, int count, HostStatus* out,
+                               hipStream_t stream);
 
 // energy_out (device u64) += sum over cells of floor(d(G[p], T[p]) * 2^s).
 hipError_t launch_energy(const void* G, const void* T, int64_t n, int dp, int storage, int s,
