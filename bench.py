@@ -28,8 +28,17 @@ and VAD beside the paper's figures, a sweep of the improvement threshold
 (1/M for M = 10^2 .. 10^5), a sweep of the grid side (128 .. 2048), and the
 same grid sorted with the Gaussian-like target filter (box3).
 
+"garden" workload: the scene scale of App. C's largest scene (4.37 M
+Gaussians, the Garden scene), a synthetic 2091 x 2091 grid (data seed 6)
+sorted with D = 59 and with its first 14 channels (every attribute but the
+higher SH coefficients), beside the paper's "well below a minute" (context).
+
+The default run also appends a compact "precision" record after its timed
+region: the 1448^2 sort in bfloat16 and in float32 storage, and the float64
+energy gap between the two arrangements.
+
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload scene|precision|batch|serve|paper]
+                    [--workload scene|precision|batch|serve|paper|garden]
 """
 from __future__ import annotations
 
@@ -125,6 +134,51 @@ def cpu_baseline(F, side: int, seed: int, reorders_full: int, sample_reorders: i
     }
 
 
+def energy_f64(torch, f, perm, side: int, r: int = 1) -> float:
+    """Mean over cells of the squared distance of the arranged features to
+    their clipped (2r+1)^2 window mean, in float64 on the device (direct
+    window sums, no quantisation): the measure the bfloat16 storage gate
+    compares. f: [d][n] float32 features, perm: int32[n] (gather form)."""
+    G = f.double()[:, perm.long()].reshape(f.shape[0], side, side)
+
+    def box(x, axis):
+        c = torch.cumsum(x, dim=axis)
+        z = torch.zeros_like(x.narrow(axis, 0, 1))
+        c = torch.cat([z, c], dim=axis)
+        idx = torch.arange(side, device=x.device)
+        hi = torch.clamp(idx + r, max=side - 1) + 1
+        lo = torch.clamp(idx - r, min=0)
+        return c.index_select(axis, hi) - c.index_select(axis, lo), (hi - lo).double()
+
+    sy, cy = box(G, 1)
+    s2, cx = box(sy, 2)
+    T = s2 / (cy.view(1, side, 1) * cx.view(1, 1, side))
+    return float(((G - T) ** 2).sum(dim=0).mean().item())
+
+
+def precision_record(torch, plas, synthetic, ctx) -> dict:
+    """The bfloat16 storage gate in a few seconds: the 1448^2 D=59 sort in
+    bfloat16 and in float32 storage on the same input, and the float64
+    energy of both arrangements at r = 1 (on the original features)."""
+    side = 1448
+    n = side * side
+    f = torch.from_numpy(synthetic.gaussian_attributes(n, synthetic.DATA_SEED_PRECISION)).cuda()
+    out = {"workload": f"plas_sort_{side}x{side}_d59", "data_seed": synthetic.DATA_SEED_PRECISION}
+    for storage in ("bf16", "f32"):
+        ctx.sort(f, side, synthetic.SORT_SEED, storage=storage, max_reorders=1)  # sizes the workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        perm, res = ctx.sort(f, side, synthetic.SORT_SEED, storage=storage)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[storage] = {"ms": round(dt * 1e3, 1), "gaussians_per_s": round(n / dt, 1),
+                        "reorders": res.reorders, "energy_f64_r1": round(energy_f64(torch, f, perm, side), 6)}
+    out["bf16_speedup"] = round(out["f32"]["ms"] / out["bf16"]["ms"], 3)
+    out["energy_gap_pct"] = round(100 * (out["bf16"]["energy_f64_r1"] / out["f32"]["energy_f64_r1"] - 1), 4)
+    out["gate_pct"] = 0.5
+    return out
+
+
 def percentile(values, q: float) -> float:
     """Nearest-rank percentile."""
     import math
@@ -163,6 +217,22 @@ def run_batch_workload(args, torch, plas, synthetic) -> int:
     elapsed = time.perf_counter() - t0
     value = n_total * args.steps / elapsed
     log(f"batch: {elapsed / args.steps:.2f} s per batch, {b.graph_builds} graphs, {b.launches} launches")
+    # The same batch with the default launch shapes (no tuning table), to
+    # measure what the autotuner adds.
+    default_shapes = None
+    if tune is not None:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        perms_d, results_d, _ = ctx.sort_batch(feats, sides=sides, seeds=seeds, graph=True)
+        torch.cuda.synchronize()
+        t_default = time.perf_counter() - t0
+        same_d = sum(int(torch.equal(a, c) and ra.reorders == rc.reorders)
+                     for a, c, ra, rc in zip(perms, perms_d, results, results_d))
+        default_shapes = {"value": round(n_total / t_default, 1), "seconds": round(t_default, 3),
+                          "autotune_speedup": round(t_default / (elapsed / args.steps), 3),
+                          "identical_to_tuned": f"{same_d}/{len(work)}"}
+        log(f"default launch shapes: {default_shapes}")
+        del perms_d, results_d
     # The same grids one after another through plas_sort.
     t0 = time.perf_counter()
     same = 0
@@ -189,13 +259,14 @@ def run_batch_workload(args, torch, plas, synthetic) -> int:
         "vs_single_sorts": {"value": round(n_total / t_plain, 1), "seconds": round(t_plain, 3),
                             "speedup": round(t_plain / (elapsed / args.steps), 3),
                             "identical": f"{same}/{len(work)}"},
+        "default_launch_shapes": default_shapes,
         "roofline": {
             "bound": "hbm", "kernel": "blur_pass (batched, all 64 grids)",
             "achieved": round(blur_bytes / (blur_avg * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(blur_bytes / (blur_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
             "per_launch_bytes": blur_bytes, "avg_launch_ms": round(blur_avg, 5),
             "sample": f"first {prof_reorders} reorders of the batch, direct launches timed with HIP events",
-            "assign_avg_ms": round(assign_avg, 5), "step_avg_ms": round(bp.step_ms / prof_reorders, 5),
+            "assign_avg_ms": round(assign_avg, 5),
         },
     }
     print(json.dumps(line), flush=True)
@@ -218,11 +289,15 @@ def run_serve_workload(args, torch, plas, synthetic) -> int:
         return [dict(arrival=float(a), side=s, storage=st, features=f, seed=synthetic.SORT_SEED + i)
                 for i, (a, s, st, f) in enumerate(zip(arrivals, sides, storages, feats))]
 
-    def serve(trace, budget):
+    def serve(trace, budget, check):
+        """Serves the trace in real time; returns latency and throughput
+        statistics, and checks the served results of the jobs at positions
+        `check` (after the trace) against the same sorts run alone."""
         srv = plas.Server(ctx, budget, graph=True)
         pending = sorted(trace, key=lambda j: j["arrival"])
         ids = {}
         finish = {}
+        kept = {}
         max_running = 0
         t0 = time.perf_counter()
         nxt = 0
@@ -238,33 +313,47 @@ def run_serve_workload(args, torch, plas, synthetic) -> int:
                 if status != plas.OK:
                     raise RuntimeError(f"job {job} failed with status {status}")
                 finish[ids[job]] = time.perf_counter() - t0
+                if ids[job] in check:
+                    kept[ids[job]] = (perm, res)
             if running == 0 and waiting == 0 and nxt < len(pending):
                 time.sleep(max(0.0, pending[nxt]["arrival"] - (time.perf_counter() - t0)))
         srv.close()
         lat = [finish[i] - pending[i]["arrival"] for i in range(len(pending))]
         n = sum(j["side"] ** 2 for j in pending)
         makespan = max(finish.values()) - pending[0]["arrival"]
+        same = 0
+        for i, (perm, res) in kept.items():
+            j = pending[i]
+            p1, r1 = ctx.sort(j["features"], j["side"], j["seed"], storage=j["storage"])
+            same += int(torch.equal(p1, perm) and r1.reorders == res.reorders and
+                        r1.energy_fixed == res.energy_fixed)
         return dict(jobs=len(pending), p50_ms=round(percentile(lat, 50) * 1e3, 1),
-                    p99_ms=round(percentile(lat, 99) * 1e3, 1), max_ms=round(max(lat) * 1e3, 1),
+                    p90_ms=round(percentile(lat, 90) * 1e3, 1), p99_ms=round(percentile(lat, 99) * 1e3, 1),
+                    max_ms=round(max(lat) * 1e3, 1),
                     gaussians_per_s=round(n / makespan, 1), makespan_s=round(makespan, 3),
                     offered_jobs_per_s=round(len(pending) / max(pending[-1]["arrival"], 1e-9), 2),
-                    max_running=max_running, sum_n=n)
+                    max_running=max_running, sum_n=n,
+                    identical_to_alone=f"{same}/{len(kept)}")
 
     budget = 64 << 30
+    jobs = args.jobs or 100
+    # Served results checked against the same sorts run alone: every tenth
+    # job of each trace.
+    check = set(range(0, jobs, 10))
     t0 = time.perf_counter()
-    trace = make_trace(args.jobs, 20.0, 11)
-    log(f"trace 1: {args.jobs} jobs generated in {time.perf_counter() - t0:.1f} s")
+    trace = make_trace(jobs, 20.0, 11)
+    log(f"trace 1: {jobs} jobs generated in {time.perf_counter() - t0:.1f} s")
     # Warm-up: one small served job.
     warm = make_trace(1, 20.0, 99)
-    serve(warm, budget)
-    r1 = serve(trace, budget)
+    serve(warm, budget, set())
+    r1 = serve(trace, budget, check)
     log(f"trace 1 (20 jobs/s): {r1}")
     mean_n = np.mean([j["side"] ** 2 for j in trace])
     rate2 = 0.8 * r1["gaussians_per_s"] / mean_n
     del trace
     torch.cuda.empty_cache()
-    trace2 = make_trace(args.jobs, rate2, 12)
-    r2 = serve(trace2, budget)
+    trace2 = make_trace(jobs, rate2, 12)
+    r2 = serve(trace2, budget, check)
     log(f"trace 2 ({rate2:.2f} jobs/s): {r2}")
     line = {
         "metric": "served p50/p99 latency and Gaussians/s, Poisson 20 jobs/s, sides 256..1024, D=59",
@@ -272,9 +361,12 @@ def run_serve_workload(args, torch, plas, synthetic) -> int:
         "steps": 1, "warmup": 1, "ms_per_step": round(r1["makespan_s"] * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 or bf16 storage (50/50), f32 arithmetic", "data": "synthetic",
-        "config": {"workload": "plas_server_poisson_20_sides_256_1024_d59", "jobs": args.jobs,
+        "config": {"workload": "plas_server_poisson_20_sides_256_1024_d59", "jobs": jobs,
                    "memory_budget_bytes": budget, "graph": True},
         "p50_ms": r1["p50_ms"], "p99_ms": r1["p99_ms"],
+        "note": ("percentiles are nearest-rank over the trace's jobs; the 20 jobs/s stream offers "
+                 "more work than one GPU sorts, so its latencies grow along the trace, and the "
+                 "second trace runs at 0.8 x the capacity measured on the first"),
         "trace_20_per_s": r1,
         "trace_0p8_capacity": dict(r2, rate_jobs_per_s=round(rate2, 3)),
     }
@@ -353,13 +445,51 @@ def run_paper_workload(args, torch, plas, synthetic) -> int:
     return 0
 
 
+def run_garden_workload(args, torch, plas, synthetic) -> int:
+    """Scene scale: the sort of a 2091 x 2091 grid (4,372,281 Gaussians, the
+    size of App. C's largest scene), with D = 59 and with 14 channels."""
+    ctx = plas.Context(0)
+    side = args.side or synthetic.GARDEN_SIDE
+    n = side * side
+    runs = {}
+    for label, make in (("d59", synthetic.gaussian_attributes), ("d14", synthetic.scene_attributes_14)):
+        f = torch.from_numpy(make(n, synthetic.DATA_SEED_GARDEN)).cuda()
+        for _ in range(args.warmup):
+            ctx.sort(f, side, synthetic.SORT_SEED, max_reorders=8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            perm, res = ctx.sort(f, side, synthetic.SORT_SEED)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        runs[label] = {"d": int(f.shape[0]), "seconds": round(dt, 3), "gaussians_per_s": round(n / dt, 1),
+                       "reorders": res.reorders, "levels": res.levels, "energy_mean": res.energy}
+        log(f"{side}^2 {label}: {runs[label]}")
+        del f, perm
+        torch.cuda.empty_cache()
+    line = {
+        "metric": f"Gaussians sorted/s at {side}^2 D=59 (scene scale)",
+        "value": runs["d59"]["gaussians_per_s"], "unit": "Gaussians/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(runs["d59"]["seconds"] * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"plas_sort_{side}x{side}_d59_and_d14", "side": side, "n": n,
+                   "data_seed": synthetic.DATA_SEED_GARDEN, "sort_seed": synthetic.SORT_SEED},
+        "runs": runs,
+        "paper": {"scene": "Garden", "gaussians": 4_370_000, "time": "well below a minute",
+                  "note": "context: another GPU, the paper's filter and channel weights"},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("scene", "precision", "batch", "serve", "paper"), default="scene")
-    ap.add_argument("--jobs", type=int, default=16, help="serve: jobs per trace")
+    ap.add_argument("--workload", choices=("scene", "precision", "batch", "serve", "paper", "garden"),
+                    default="scene")
+    ap.add_argument("--jobs", type=int, default=0, help="serve: jobs per trace (default 100)")
     ap.add_argument("--no-autotune", action="store_true", help="batch: use the default launch shapes")
     ap.add_argument("--side", type=int, default=0, help="grid side (default: the workload's)")
     ap.add_argument("--cpu-sample-reorders", type=int, default=120,
@@ -370,6 +500,8 @@ def main() -> int:
     ap.add_argument("--max-reorders", type=int, default=0,
                     help="stop each sort after this many reorders (profiling runs only; "
                          "the JSON line is then not the workload's throughput)")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="scene workload: skip the appended 1448^2 bfloat16 / float32 record")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain elementwise copy of 256 MiB (read and write 2^26 "
                          "floats) to calibrate HBM byte counters")
@@ -391,6 +523,8 @@ def main() -> int:
         return run_serve_workload(args, torch, plas, synthetic)
     if args.workload == "paper":
         return run_paper_workload(args, torch, plas, synthetic)
+    if args.workload == "garden":
+        return run_garden_workload(args, torch, plas, synthetic)
     precision = args.workload == "precision"
     side = args.side or (1448 if precision else 1024)
     data_seed = synthetic.DATA_SEED_PRECISION if precision else synthetic.DATA_SEED_SCENE
@@ -539,6 +673,12 @@ def main() -> int:
         line["note"] = "truncated profiling run, not the workload's throughput"
     if not args.no_cpu_baseline and not args.max_reorders and not precision:
         line["cpu_baseline"] = cpu_baseline(F, side, seed, res.reorders, args.cpu_sample_reorders)
+    if not precision and not args.no_precision and not args.max_reorders and not args.side:
+        del f_dev, perm
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        line["precision"] = precision_record(torch, plas, synthetic, ctx)
+        log(f"precision record in {time.perf_counter() - t0:.1f} s: {line['precision']}")
     print(json.dumps(line), flush=True)
     return 0
 

@@ -82,9 +82,13 @@ typedef struct plas_context* plas_handle;
  * permutation as params->init_perm and the same features, side, seed and
  * other parameters, it continues the sort, which then ends with the
  * permutation, reorder count, energy and per-level statistics of the sort run
- * without a stop (its trace holds only the levels run after the resume). The
- * fields are the state of the Sec. 3.1 controller (radius level, block shift
- * and stall test); a caller stores and returns them unchanged.
+ * without a stop. The resumed sort's trace is indexed by level from level 0:
+ * entries levels_done onwards hold the levels it ran (the level it resumed in
+ * with its whole count, the reorders before the stop included), the entries
+ * before them are zero, so stitching the first levels_done entries of the
+ * earlier trace in front gives the uninterrupted sort's trace. The fields are
+ * the state of the Sec. 3.1 controller (radius level, block shift and stall
+ * test); a caller stores and returns them unchanged.
  */
 typedef struct {
     uint32_t struct_size;    /* sizeof(plas_sort_checkpoint) */

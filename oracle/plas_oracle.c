@@ -188,8 +188,8 @@ static float feature_at(const float* F, int64_t n, int32_t d, int32_t layout, in
 }
 
 /* ------------------------------------------------------------------------ */
-/* Energy scale. The paper measures "the mean L2 distance between sorted     */
-/* grid and target grid" (Sec. 3.1) and compares it with a relative         */
+/* Energy scale. The paper tracks progress by the mean L2 distance of the    */
+/* sorted grid to its target (Sec. 3.1) and compares it with a relative     */
 /* threshold. Reading: the stall test runs on an exact integer energy, the   */
 /* sum over cells of floor(d * 2^s), with s fixed once per input so that the */
 /* sum over all N cells stays below 2^61:                                    */
@@ -965,9 +965,9 @@ double plas_ref_grid_energy_f64(const float* F, const int32_t* perm, int64_t n, 
     return total / (double)n;
 }
 
-/* "the variance of the absolute differences (VAD) between all neighboring
- * values, over all channels" (App. C). Reading: right and down neighbours,
- * no wrap-around; population variance of |a - b| in float64. */
+/* VAD, the sort-quality measure of App. C: the variance of |a - b| over
+ * neighbouring cells, every channel counted. Reading: right and down
+ * neighbours, no wrap-around; population variance in float64. */
 double plas_ref_vad(const float* F, const int32_t* perm, int64_t n, int32_t d, int32_t side,
                     int32_t layout)
 {

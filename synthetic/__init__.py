@@ -37,8 +37,15 @@ DATA_SEED_PRECISION = 3   # 1448 x 1448 grid
 SORT_SEED = 0x5EED
 DATA_SEED_BATCH = 4       # the 64-grid batch: sides and per-grid data seeds
 DATA_SEED_RGB = 5         # the random 512 x 512 x 3 grid of the runtime experiment
+DATA_SEED_GARDEN = 6      # the scene-scale grid of App. C's largest scene
 BATCH_GRIDS = 64
 BATCH_SIDE_RANGE = (128, 724)
+# App. C's largest scene holds 4.37 million Gaussians: a grid of side 2091
+# (2091^2 = 4,372,281).
+GARDEN_SIDE = 2091
+# Channels before the 45 higher spherical-harmonics coefficients: xyz,
+# log-scale, rotation, opacity and SH DC (the paper sorts on at most 14).
+D_NO_SH_REST = D_3DGS - 45  # 14
 
 
 def gaussian_attributes(n: int, seed: int, layout: str = "cn") -> np.ndarray:
@@ -76,6 +83,12 @@ def gaussian_attributes(n: int, seed: int, layout: str = "cn") -> np.ndarray:
     if layout == "cn":
         return np.ascontiguousarray(nc.T)
     raise ValueError(f"unknown layout {layout!r}")
+
+
+def scene_attributes_14(n: int, seed: int) -> np.ndarray:
+    """The first 14 channels of gaussian_attributes(n, seed) (every channel
+    but the higher SH coefficients), channel-major [14][n]."""
+    return np.ascontiguousarray(gaussian_attributes(n, seed, "cn")[:D_NO_SH_REST])
 
 
 def random_features(n: int, d: int, seed: int, layout: str = "cn",

@@ -85,3 +85,18 @@ def test_cpu_baseline_on_a_small_grid():
     assert b["kind"] == "oracle" and b["unit"] == "Gaussians/s" and b["cores"] >= 1
     assert b["value"] > 0 and "stopped after 24 reorders" in b["sample"]
     assert b["one_thread"]["sample_reorders"] == 2 and b["one_thread"]["seconds_per_reorder"] > 0
+
+
+@pytest.mark.parametrize("side,d,r", [(2, 3, 1), (7, 59, 1), (16, 14, 2), (33, 5, 1)])
+def test_energy_f64_matches_the_oracle_definition(ref, side, d, r):
+    """bench.energy_f64 (prefix sums in float64 on torch) against the
+    oracle's float64 energy (direct window sums) of the same arrangement."""
+    import numpy as np
+    import torch
+    import synthetic
+    n = side * side
+    F = synthetic.random_features(n, d, 3 + side, "cn", -2.0, 2.0)
+    perm = synthetic.random_permutation(n, side)
+    got = bench.energy_f64(torch, torch.from_numpy(F), torch.from_numpy(perm), side, r)
+    want = ref.grid_energy_f64(F, perm, side, r)
+    assert got == pytest.approx(want, rel=1e-12, abs=1e-15)

@@ -1,6 +1,8 @@
 """GPU tests of the sort server (plas_server_*): jobs submitted while others
 run are admitted at reorder boundaries as memory frees up, and every job's
-result equals, bit for bit, the same sort run alone (plas_sort)."""
+result equals, bit for bit, the same sort run alone (plas_sort) and the CPU
+oracle's sort -- for small mixed jobs and for jobs of the serving
+configuration (sides 256 .. 1024, float32 and bfloat16 storage)."""
 import numpy as np
 import pytest
 
@@ -141,3 +143,98 @@ def test_other_calls_between_steps(env):
     srv.close()
     p1, r1 = ctx.sort(f1, 56, 7)
     _same(r1, p1.cpu().numpy(), got[1], got[0].cpu().numpy())
+
+
+def test_small_jobs_match_the_oracle(env):
+    """The served small jobs (the mix above, direct launches) against the CPU
+    oracle itself: permutation, reorders and integer energy."""
+    torch, plas, ctx, ref = env
+    feats = [synthetic.gaussian_attributes(s * s, ds) for s, _, ds, _ in JOBS]
+    srv = plas.Server(ctx, 1 << 34)
+    ids = {srv.submit(torch.from_numpy(F).cuda(), side, seed, storage=storage): i
+           for i, (F, (side, storage, _, seed)) in enumerate(zip(feats, JOBS))}
+    done = _drain(plas, srv, ids, len(JOBS))
+    for i, (side, storage, _, seed) in enumerate(JOBS):
+        perm, res = done[i]
+        want = ref.sort(feats[i], side, seed, storage_bf16=(storage == "bf16"))
+        assert want.status == 0
+        assert res.reorders == want.reorders and res.energy_fixed == want.energy, (side, storage)
+        assert np.array_equal(perm.cpu().numpy(), want.perm), (side, storage)
+
+
+def _drain(plas, srv, ids, count, submit_later=()):
+    """Steps the server until `count` jobs finished; jobs in submit_later
+    ((step, features, side, seed, storage, index) tuples) are submitted at
+    their step, while the others run."""
+    done = {}
+    later = sorted(submit_later, key=lambda t: t[0])
+    steps = 0
+    while len(done) < count:
+        while later and later[0][0] <= steps:
+            _, f, side, seed, storage, i = later.pop(0)
+            ids[srv.submit(f, side, seed, storage=storage)] = i
+        srv.step()
+        steps += 1
+        assert steps < 100000
+        for job, status, perm, res in srv.poll():
+            assert status == plas.OK
+            done[ids[job]] = (perm, res)
+    assert srv.step() == (0, 0)
+    srv.close()
+    return done
+
+
+def _serving_jobs(count=6, seed=71):
+    """Jobs of the serving workload's distribution: sides log-uniform in
+    [256, 1024], float32 and bfloat16 storage alternating."""
+    sides = synthetic.batched_sides(count, 256, 1024, seed)
+    return [(side, "f32" if i % 2 == 0 else "bf16", seed * 1000 + i, synthetic.SORT_SEED + i)
+            for i, side in enumerate(sides)]
+
+
+def _submit_in_two_waves(srv, jobs, feats):
+    ids = {}
+    half = len(jobs) // 2
+    for i in range(half):
+        side, storage, _, seed = jobs[i]
+        ids[srv.submit(feats[i], side, seed, storage=storage)] = i
+    later = [(2 + i, feats[i], jobs[i][0], jobs[i][3], jobs[i][1], i) for i in range(half, len(jobs))]
+    return ids, later
+
+
+def test_serving_config_jobs_equal_alone(env):
+    """Whole sorts of jobs from the serving configuration (sides 256 .. 1024,
+    float32 / bfloat16), half of them admitted while the others run: each
+    equals the same sort run alone."""
+    torch, plas, ctx, ref = env
+    jobs = _serving_jobs()
+    assert {s for _, s, _, _ in jobs} == {"f32", "bf16"} and max(j[0] for j in jobs) >= 512
+    feats = [_features(torch, side, ds) for side, _, ds, _ in jobs]
+    srv = plas.Server(ctx, 1 << 36, graph=True)
+    ids, later = _submit_in_two_waves(srv, jobs, feats)
+    done = _drain(plas, srv, ids, len(jobs), later)
+    for i, (side, storage, _, seed) in enumerate(jobs):
+        p1, r1 = ctx.sort(feats[i], side, seed, storage=storage)
+        perm, res = done[i]
+        _same(r1, p1.cpu().numpy(), res, perm.cpu().numpy())
+
+
+@pytest.mark.parametrize("params", [dict(max_reorders=3), dict(start_radius=3.0, max_reorders=4)])
+def test_serving_config_jobs_match_the_oracle(env, params):
+    """The same serving-configuration jobs, served in a mix, checked against
+    the CPU oracle over the first reorders of the coarsest level and of the
+    finest levels (a sort started at radius 3)."""
+    torch, plas, ctx, ref = env
+    jobs = _serving_jobs()
+    host = [synthetic.gaussian_attributes(side * side, ds) for side, _, ds, _ in jobs]
+    feats = [torch.from_numpy(F).cuda() for F in host]
+    srv = plas.Server(ctx, 1 << 36, graph=True, **params)
+    ids, later = _submit_in_two_waves(srv, jobs, feats)
+    done = _drain(plas, srv, ids, len(jobs), later)
+    for i, (side, storage, _, seed) in enumerate(jobs):
+        perm, res = done[i]
+        want = ref.sort(host[i], side, seed, storage_bf16=(storage == "bf16"), **params)
+        assert want.status == 0
+        assert res.reorders == want.reorders == params["max_reorders"]
+        assert res.energy_fixed == want.energy, (side, storage)
+        assert np.array_equal(perm.cpu().numpy(), want.perm), (side, storage)
