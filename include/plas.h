@@ -203,6 +203,22 @@ int32_t plas_grid_energy(plas_handle h, const void* features, const int32_t* per
                          double* energy_mean);
 
 /*
+ * plas_grid_energy for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid hipMalloc): the same arguments and
+ * results, computed in a static device
+ * array of about 50 MB that the library holds on each GPU it runs on until
+ * the process ends. Limit: n <= 65536 cells (side <= 256), else
+ * PLAS_ERR_INVALID_ARGUMENT. The call allocates nothing (no hipMalloc,
+ * hipFree or memset; it does synchronise h's stream to read its results).
+ * Every call on one GPU shares that array: calls that overlap on a GPU (other
+ * threads, other streams) race; each call leaves its data there.
+ */
+int32_t plas_grid_energy_noalloc(plas_handle h, const void* features, const int32_t* perm, int64_t n,
+                                 int32_t d, int32_t side, int32_t layout, int32_t dtype, int32_t storage,
+                                 int32_t radius, uint64_t* energy_fixed, int32_t* scale_shift,
+                                 double* energy_mean);
+
+/*
  * VAD, the sort-quality measure of App. C: the population variance of the
  * absolute differences |a - b| between the values of right and down
  * neighbouring cells (no wrap-around) of the arranged grid

@@ -42,7 +42,8 @@ MAX_CHANNELS = 64
 # include/plas_batch.h.
 EXPORTS = (
     "plas_get_abi_version", "plas_sort_params_init", "plas_create", "plas_destroy",
-    "plas_set_stream", "plas_sort", "plas_grid_energy", "plas_status_string", "plas_last_error",
+    "plas_set_stream", "plas_sort", "plas_grid_energy", "plas_grid_energy_noalloc", "plas_status_string",
+    "plas_last_error",
     "plas_vad", "plas_stage_blur", "plas_stage_group_table", "plas_stage_assign", "plas_stage_energy",
     "plas_stage_bijection", "plas_philox4x64_10", "plas_draw", "plas_schedule",
     "plas_scale_shift_from_ranges",
@@ -210,6 +211,8 @@ def library() -> ctypes.CDLL:
                             ctypes.POINTER(SortStats)]),
         "plas_grid_energy": (i32, [vp, vp, vp, i64, i32, i32, i32, i32, i32, i32, u64p, i32p,
                                    ctypes.POINTER(ctypes.c_double)]),
+        "plas_grid_energy_noalloc": (i32, [vp, vp, vp, i64, i32, i32, i32, i32, i32, i32, u64p, i32p,
+                                           ctypes.POINTER(ctypes.c_double)]),
         "plas_vad": (i32, [vp, vp, vp, i64, i32, i32, i32, i32, ctypes.POINTER(ctypes.c_double)]),
         "plas_status_string": (ctypes.c_char_p, [i32]),
         "plas_last_error": (ctypes.c_char_p, [vp]),
@@ -472,8 +475,10 @@ class Context:
                      assign_blocks=t.assign_blocks) for t in table[: entries.value]]
 
     def grid_energy(self, features, perm=None, side: int | None = None, radius: int = 1,
-                    layout: str = "cn", storage: str = "f32"):
-        """(energy_fixed, scale_shift, energy_mean) of features[perm] at radius."""
+                    layout: str = "cn", storage: str = "f32", noalloc: bool = False):
+        """(energy_fixed, scale_shift, energy_mean) of features[perm] at radius.
+        noalloc: through plas_grid_energy_noalloc (n <= 65536, no device
+        allocation)."""
         import torch
         dtype = _feature_dtype(features)
         if layout == "cn":
@@ -490,10 +495,11 @@ class Context:
             p = ctypes.c_void_p(perm.data_ptr())
         E, s, mean = ctypes.c_uint64(), ctypes.c_int32(), ctypes.c_double()
         self._bind_stream()
-        st = library().plas_grid_energy(self._h, ctypes.c_void_p(features.data_ptr()), p, n, d, side,
-                                        lay, dtype, STORAGES[storage], radius, ctypes.byref(E),
-                                        ctypes.byref(s), ctypes.byref(mean))
-        self._check(st, "plas_grid_energy")
+        name = "plas_grid_energy_noalloc" if noalloc else "plas_grid_energy"
+        st = getattr(library(), name)(self._h, ctypes.c_void_p(features.data_ptr()), p, n, d, side,
+                                      lay, dtype, STORAGES[storage], radius, ctypes.byref(E),
+                                      ctypes.byref(s), ctypes.byref(mean))
+        self._check(st, name)
         return int(E.value), s.value, mean.value
 
     def vad(self, features, perm=None, side: int | None = None, layout: str = "cn") -> float:

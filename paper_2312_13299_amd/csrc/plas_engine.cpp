@@ -92,6 +92,12 @@ int32_t plas_create(plas_handle* out, int32_t device) {
     plas_destroy(h);
     return PLAS_ERR_OUT_OF_MEMORY;
   }
+  // The no-allocation energy query's scratch on this device (its address,
+  // looked up once per device with the device current).
+  if (plas::noalloc_scratch(device, &h->noalloc) != hipSuccess) {
+    plas_destroy(h);
+    return PLAS_ERR_HIP;
+  }
   *out = h;
   return PLAS_OK;
 }
@@ -324,6 +330,66 @@ int32_t plas_grid_energy(plas_handle h, const void* features, const int32_t* per
   PLAS_HIP(h, plas::launch_blur_pass(H, T, side, dp, storage, nullptr, radius, 1, as<float>(h->inv), h->stream));
   unsigned long long* acc = as<unsigned long long>(h->scratch);
   PLAS_HIP(h, hipMemsetAsync(acc, 0, sizeof(unsigned long long), h->stream));
+  PLAS_HIP(h, plas::launch_energy(G, T, n, dp, storage, s, acc, h->stream));
+  PLAS_HIP(h, hipMemcpyAsync(h->u64_host, acc, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
+  PLAS_HIP(h, hipStreamSynchronize(h->stream));
+  const uint64_t E = h->u64_host[0];
+  if (energy_fixed) *energy_fixed = E;
+  if (scale_shift_out) *scale_shift_out = s;
+  if (energy_mean) *energy_mean = std::ldexp(static_cast<double>(E), -s) / static_cast<double>(n);
+  return PLAS_OK;
+}
+
+int32_t plas_grid_energy_noalloc(plas_handle h, const void* features, const int32_t* perm, int64_t n, int32_t d,
+                                 int32_t side, int32_t layout, int32_t dtype, int32_t storage, int32_t radius,
+                                 uint64_t* energy_fixed, int32_t* scale_shift_out, double* energy_mean) {
+  // plas_grid_energy's steps on the device's static scratch (no allocation,
+  // no memset): ingest into T, range and scale, permutation check (counts in
+  // H), 1/c table, gather into G, rows into H, columns into T, energy.
+  using L = plas::NoAllocLayout;
+  int32_t st = check_features(h, features, n, d, side, layout, dtype);
+  if (st != PLAS_OK) return st;
+  h->error.clear();
+  if (radius < 0) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "radius must be >= 0");
+  if (!valid_storage(storage)) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "unknown storage");
+  if (n > plas::kNoAllocMaxCells)
+    return fail(h, PLAS_ERR_INVALID_ARGUMENT, "n above the no-allocation limit of 65536 cells (side 256)");
+  DeviceScope scope(h->device);
+  if (!scope.ok()) return fail(h, PLAS_ERR_HIP, "hipSetDevice failed");
+  char* base = static_cast<char*>(h->noalloc);
+  void* G = base + L::kG;
+  void* H = base + L::kH;
+  void* T = base + L::kT;
+  float* range_part = reinterpret_cast<float*>(base + L::kRangePart);
+  float* range_out = reinterpret_cast<float*>(base + L::kRangeOut);
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(base + L::kFlags);
+  int32_t* flag = reinterpret_cast<int32_t*>(base + L::kFlags + 8);
+  float* inv = reinterpret_cast<float*>(base + L::kInv);
+  const int dp = padded_channels(d);
+
+  PLAS_HIP(h, plas::launch_ingest(features, dtype == PLAS_DTYPE_BF16, n, d, layout, dp, storage, T, h->stream));
+  PLAS_HIP(h, plas::launch_range(T, n, d, dp, storage, range_part, range_out, h->stream));
+  PLAS_HIP(h, hipMemcpyAsync(h->range_host, range_out, (2 * dp + 1) * sizeof(float), hipMemcpyDeviceToHost,
+                             h->stream));
+  PLAS_HIP(h, hipStreamSynchronize(h->stream));
+  if (h->range_host[2 * dp] != 0.0f) return fail(h, PLAS_ERR_NONFINITE, "features contain NaN or infinity");
+  const int32_t s = scale_shift(h->range_host, h->range_host + dp, d, n);
+  if (perm != nullptr) {
+    int32_t* counts = static_cast<int32_t*>(H);
+    PLAS_HIP(h, plas::launch_fill_u32(reinterpret_cast<uint32_t*>(counts), n, 0u, h->stream));
+    PLAS_HIP(h, plas::launch_fill_u32(reinterpret_cast<uint32_t*>(flag), 1, 0u, h->stream));
+    PLAS_HIP(h, plas::launch_check_perm(perm, n, counts, flag, h->stream));
+    PLAS_HIP(h, hipMemcpyAsync(h->u64_host, flag, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    PLAS_HIP(h, hipStreamSynchronize(h->stream));
+    int32_t bad = 0;
+    std::memcpy(&bad, h->u64_host, sizeof(int32_t));
+    if (bad != 0) return fail(h, PLAS_ERR_INVALID_ARGUMENT, "permutation is not a bijection of [0, n)");
+  }
+  PLAS_HIP(h, plas::launch_inverse_counts(inv, side, h->stream));
+  PLAS_HIP(h, plas::launch_gather(T, perm, G, n, dp, storage, h->stream));
+  PLAS_HIP(h, plas::launch_blur_pass(G, H, side, dp, storage, nullptr, radius, 0, inv, h->stream));
+  PLAS_HIP(h, plas::launch_blur_pass(H, T, side, dp, storage, nullptr, radius, 1, inv, h->stream));
+  PLAS_HIP(h, plas::launch_fill_u32(reinterpret_cast<uint32_t*>(acc), 2, 0u, h->stream));
   PLAS_HIP(h, plas::launch_energy(G, T, n, dp, storage, s, acc, h->stream));
   PLAS_HIP(h, hipMemcpyAsync(h->u64_host, acc, sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream));
   PLAS_HIP(h, hipStreamSynchronize(h->stream));

@@ -60,6 +60,7 @@ struct plas_context {
   plas_host::DeviceBuffer stage_state;             // DevState of a stage call
   plas_host::DeviceBuffer scratch;                 // u64 accumulators and flags
   plas_host::DeviceBuffer vad;                     // VAD partial sums and results
+  void* noalloc = nullptr;                         // the device's scratch of plas_grid_energy_noalloc
   // Pinned host memory for small read-backs.
   HostStatus* status_host = nullptr;
   float* range_host = nullptr;

@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <cstddef>
+#include <mutex>
 
 #include "plas_launch.h"
 #include "plas_random.h"
@@ -1637,9 +1638,61 @@ __global__ __launch_bounds__(kBlock) void k_batch_status(const BatchGrid* __rest
   out[i] = hs;
 }
 
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* __restrict__ p, int64_t count, uint32_t value) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < count; i += stride) p[i] = value;
+}
+
+__global__ __launch_bounds__(kBlock) void k_inverse_counts(float* __restrict__ inv, int w) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c <= w) inv[c] = c == 0 ? 0.0f : 1.0f / static_cast<float>(c);
+}
+
 }  // namespace
 
+// ------------------------------------------------- no-allocation scratch
+
+// The device memory of plas_grid_energy_noalloc: its three grids, the range
+// pass scratch, an accumulator and a flag, and the 1/c table. Host code
+// must not pass `scratch` itself to a kernel (it names a host-side stand-in):
+// noalloc_scratch gives its address on the current device.
+static __device__ __align__(256) unsigned char scratch[NoAllocLayout::kBytes];
+static_assert(NoAllocLayout::kRangePartBytes == static_cast<size_t>(kRangeBlocks) * 3 * 64 * sizeof(float),
+              "range scratch of the widest cell");
+static_assert((kNoAllocMaxSide + 1) * sizeof(float) <= 4096, "1/c table");
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_address[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, void** out) {
+  if (out == nullptr || device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidValue;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_address[device] == nullptr) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_address[device] = ptr;
+  }
+  *out = g_scratch_address[device];
+  return hipSuccess;
+}
+
 // --------------------------------------------------------------- launchers
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  k_fill_u32<<<blocks_for(count, 1024), kBlock, 0, stream>>>(p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_inverse_counts(float* inv, int w, hipStream_t stream) {
+  if (w < 0) return hipErrorInvalidValue;
+  k_inverse_counts<<<(w + kBlock) / kBlock, kBlock, 0, stream>>>(inv, w);
+  return hipGetLastError();
+}
 
 #define PLAS_DISPATCH_DP(dp, CALL) \
   switch (dp) {                    \

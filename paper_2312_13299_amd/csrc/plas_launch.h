@@ -113,4 +113,29 @@ hipError_t launch_batch_status(const BatchGrid* grids, const int32_t* list, int 
 hipError_t launch_energy(const void* G, const void* T, int64_t n, int dp, int storage, int s,
                          unsigned long long* energy_out, hipStream_t stream);
 
+// p[i] = value for i < count (a kernel, not a memset: callers may capture the
+// stream in a graph).
+hipError_t launch_fill_u32(uint32_t* p, int64_t count, uint32_t value, hipStream_t stream);
+// inv[c] = float32 1/c (correctly rounded) for c = 1..w, inv[0] = 0.
+hipError_t launch_inverse_counts(float* inv, int w, hipStream_t stream);
+
+// ---- the device scratch of the no-allocation energy query. One array per
+// GPU, allocated with the code object and held until the process ends;
+// every call on a GPU shares it.
+constexpr int64_t kNoAllocMaxCells = 65536;  // side <= 256
+constexpr int kNoAllocMaxSide = 256;
+struct NoAllocLayout {
+  static constexpr size_t kGrid = static_cast<size_t>(kNoAllocMaxCells) * 64 * 4;  // widest cell, float32
+  static constexpr size_t kG = 0, kH = kGrid, kT = 2 * kGrid;
+  static constexpr size_t kRangePart = 3 * kGrid;
+  static constexpr size_t kRangePartBytes = 256 * 3 * 64 * 4;  // range_partial_floats(64) floats
+  static constexpr size_t kRangeOut = kRangePart + kRangePartBytes;
+  static constexpr size_t kFlags = kRangeOut + 1024;  // u64 accumulator, then an int32 flag
+  static constexpr size_t kInv = kFlags + 256;
+  static constexpr size_t kBytes = kInv + 4096;  // (kNoAllocMaxSide + 1) floats, rounded up
+};
+// The array's device address on `device`, which must be current (looked up
+// once per device, then remembered).
+hipError_t noalloc_scratch(int device, void** out);
+
 }  // namespace plas
