@@ -60,6 +60,14 @@ struct DevState {
   uint64_t energy_prev;
   uint64_t energy_last;
   uint64_t level_moved;
+  // ---- prepared during a reorder's assignment for its control step (by
+  // the first block, so that the last block's step draws nothing and reads
+  // no table): block shift number j, the grouping keys of reorder k + 1 and
+  // the next level's parameters (unset at the last level)
+  int32_t next_dy;
+  int32_t next_dx;
+  uint64_t next_keys[4];
+  LevelInfo next_level;
 };
 
 // Small status block copied to pinned host memory at each sync.

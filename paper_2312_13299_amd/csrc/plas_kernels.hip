@@ -543,7 +543,7 @@ __device__ __forceinline__ Q load_quad(const Q* p) {
 // compiler does not add its own conservative wait (every load done) before
 // each LDS read; M0 (the LDS base of a load) is set in the same asm statement,
 // and no compiler-generated code of these kernels uses M0.
-template <typename S>
+template <typename S, int RR>
 struct RingShape {
   static constexpr int kRowBytes = 64 * static_cast<int>(sizeof(S));  // one position of the wave's lines
   static constexpr int kLanesPerRow = kRowBytes / 16;
@@ -556,20 +556,23 @@ struct RingShape {
 #ifndef PLAS_BLUR_EARLY
 #define PLAS_BLUR_EARLY 0
 #endif
-  static constexpr int kDepth = PLAS_BLUR_DEPTH;  // issue slots in flight, the one being summed included
+  // issue slots in flight, the one being summed included (two with the
+  // small ring, whose split halves hold two chunks)
+  static constexpr int kDepth = RR >= 128 ? PLAS_BLUR_DEPTH : 2;
   static constexpr bool kEarly = PLAS_BLUR_EARLY;  // a step issues its loads before summing (else after)
-  static constexpr int kRingRows = 128;
+  static constexpr int kRingRows = RR;
   static constexpr int kSlots = kRingRows / kChunk;
   static constexpr int kHalfRows = kRingRows / 2;  // rows of each stream when the ring is split
   static_assert(kRingRows % kChunk == 0 && (kRingRows & (kRingRows - 1)) == 0, "ring shape");
   static_assert(kHalfRows / kChunk >= kDepth + (kEarly ? 1 : 0), "a split half holds the chunks in use and in flight");
 };
 
-// LDS of one wave: 36 KB (float32) or 18 KB (bfloat16).
-template <typename S>
+// LDS of one wave: (RR + 16) rows of 256 B (float32) or 128 B (bfloat16),
+// 36 KB / 18 KB with the 128-row ring.
+template <typename S, int RR>
 struct RingLds {
-  S ring[RingShape<S>::kRingRows][64];
-  S out[RingShape<S>::kChunk][64];
+  S ring[RingShape<S, RR>::kRingRows][64];
+  S out[RingShape<S, RR>::kChunk][64];
 };
 
 // Leaving values come from the entering ring when, at every step, the chunk
@@ -577,26 +580,44 @@ struct RingLds {
 // ceil(r / kChunk) chunks between a step's chunk and its outputs and
 // ceil((r + 1) / kChunk) between an output chunk and its leaving positions,
 // A + ceil((r + 1) / kChunk) <= kSlots + 1 - kDepth.
-template <typename S>
+template <typename S, int RR>
 __device__ __forceinline__ bool ring_leave(int r) {
-  using Sh = RingShape<S>;
+  using Sh = RingShape<S, RR>;
   const int a = (r + Sh::kChunk - 1) / Sh::kChunk;
   const int b = (r + Sh::kChunk) / Sh::kChunk;
   return a + b <= Sh::kSlots + (Sh::kEarly ? 0 : 1) - Sh::kDepth;
 }
 
 // One direct load: 16 bytes per lane from `src` to LDS byte address
-// m0 + 16 * lane. A preceding LDS read of the rows it overwrites must have
-// completed: lgkmcnt(0) first.
+// m0 + 16 * lane, with a streaming hint (the data is not read again through
+// the cache) when `nt`. A preceding LDS read of the rows it overwrites must
+// have completed: lgkmcnt(0) first.
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Winline-asm"  // M0 is named as clobbered on purpose
+template <bool nt>
 __device__ __forceinline__ void dma16(const void* src, uint32_t m0) {
-  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
-               :
-               : "v"(src), "s"(m0)
-               : "memory", "m0");
+  if constexpr (nt)
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off nt"
+                 :
+                 : "v"(src), "s"(m0)
+                 : "memory", "m0");
+  else
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+                 :
+                 : "v"(src), "s"(m0)
+                 : "memory", "m0");
 }
 #pragma clang diagnostic pop
+
+// Cache hints of the two load streams: the leaving stream (a second read of
+// positions the entering stream read 2r + 1 positions earlier) streams
+// through, so that it does not evict entering data the L2 still holds for
+// it; see kBlurEnterStream for the entering stream.
+#ifndef PLAS_BLUR_ENTER_NT
+#define PLAS_BLUR_ENTER_NT 0
+#endif
+constexpr bool kBlurEnterStream = PLAS_BLUR_ENTER_NT;
+constexpr bool kBlurLeaveStream = true;
 
 // s_waitcnt vmcnt(n) for a run-time n (rounded down, which only waits
 // longer).
@@ -626,9 +647,9 @@ __device__ __forceinline__ void wait_vm_dyn(int n) {
   }
 }
 
-template <typename S, int DP>
+template <typename S, int DP, int RR>
 struct RingLine {
-  using Sh = RingShape<S>;
+  using Sh = RingShape<S, RR>;
   static constexpr int kChunk = Sh::kChunk;
   static constexpr int kPiecesPerCell = DP * static_cast<int>(sizeof(S)) / 16;
   static_assert(kPiecesPerCell >= 1, "a cell must hold at least one 16-byte piece");
@@ -646,11 +667,12 @@ struct RingLine {
   bool split;        // the leaving values have their own stream (the ring's upper half)
   int enter_mask;    // ring rows of the entering stream - 1
   uint32_t ring_m0;  // LDS byte address of ring row 0 (the same for all lanes)
-  RingLds<S>* lds;
+  RingLds<S, RR>* lds;
 
   __device__ __forceinline__ int clamp_pos(int t) const { return t < 0 ? 0 : (t > w - 1 ? w - 1 : t); }
 
   // kVec loads of chunk m (positions kChunk m ..) into rows row0 ..
+  template <bool nt>
   __device__ __forceinline__ void load_chunk(int m, int row0) const {
     const int pos0 = m * kChunk;
     const uint32_t m0 = ring_m0 + static_cast<uint32_t>(row0 * Sh::kRowBytes);
@@ -658,11 +680,11 @@ struct RingLine {
       const S* p = src + ld_off + static_cast<int64_t>(pos0 + q) * step;
       const int64_t inc = static_cast<int64_t>(Sh::kPos) * step;
 #pragma unroll
-      for (int i = 0; i < Sh::kVec; ++i) dma16(p + i * inc, m0 + i * 1024u);
+      for (int i = 0; i < Sh::kVec; ++i) dma16<nt>(p + i * inc, m0 + i * 1024u);
     } else {
 #pragma unroll
       for (int i = 0; i < Sh::kVec; ++i)
-        dma16(src + ld_off + static_cast<int64_t>(clamp_pos(pos0 + Sh::kPos * i + q)) * step, m0 + i * 1024u);
+        dma16<nt>(src + ld_off + static_cast<int64_t>(clamp_pos(pos0 + Sh::kPos * i + q)) * step, m0 + i * 1024u);
     }
   }
 
@@ -670,8 +692,9 @@ struct RingLine {
   __device__ __forceinline__ bool slot_enter(int u) const { return u < n_chunks; }
   __device__ __forceinline__ bool slot_leave(int u) const { return split && u - lag >= 0 && u - lag < n_chunks; }
   __device__ __forceinline__ void issue(int u) const {
-    if (slot_enter(u)) load_chunk(u, (u * kChunk) & enter_mask);
-    if (slot_leave(u)) load_chunk(u - lag, Sh::kHalfRows + (((u - lag) * kChunk) & (Sh::kHalfRows - 1)));
+    if (slot_enter(u)) load_chunk<kBlurEnterStream>(u, (u * kChunk) & enter_mask);
+    if (slot_leave(u))
+      load_chunk<kBlurLeaveStream>(u - lag, Sh::kHalfRows + (((u - lag) * kChunk) & (Sh::kHalfRows - 1)));
   }
   __device__ __forceinline__ int slot_loads(int u) const {
     return Sh::kVec * ((slot_enter(u) ? 1 : 0) + (slot_leave(u) ? 1 : 0));
@@ -692,13 +715,16 @@ struct RingLine {
     return n;
   }
 
+  __device__ __forceinline__ int enter_row(int x) const { return (x + r) & enter_mask; }
+  __device__ __forceinline__ int leave_row(int x) const {
+    const int t = x - r - 1;
+    return split ? Sh::kHalfRows + (t & (Sh::kHalfRows - 1)) : (t & (Sh::kRingRows - 1));
+  }
   __device__ __forceinline__ float enter_val(int x) const {
-    return Storage<S>::widen(lds->ring[(x + r) & enter_mask][lane]);
+    return Storage<S>::widen(lds->ring[enter_row(x)][lane]);
   }
   __device__ __forceinline__ float leave_val(int x) const {
-    const int t = x - r - 1;
-    const int row = split ? Sh::kHalfRows + (t & (Sh::kHalfRows - 1)) : (t & (Sh::kRingRows - 1));
-    return Storage<S>::widen(lds->ring[row][lane]);
+    return Storage<S>::widen(lds->ring[leave_row(x)][lane]);
   }
 
   // Outputs x0 .. x0 + kChunk - 1, all inside the grid, all with (ENTER) or
@@ -711,10 +737,27 @@ struct RingLine {
     constexpr bool kConstMult = ENTER == LEAVE;
     const int mult_bits = __float_as_int(mult);
     float e[kChunk], l[kChunk];
+    // The chunk's entering rows and its leaving rows are each kChunk
+    // consecutive ring rows unless they wrap around the end of their region:
+    // then one base address with constant offsets reads them.
+    const int eb = enter_row(x0), lb = leave_row(x0);
+    const bool e_flat = !ENTER || eb + kChunk <= enter_mask + 1;
+    const bool l_flat = !LEAVE || (lb & (split ? Sh::kHalfRows - 1 : Sh::kRingRows - 1)) + kChunk <=
+                                      (split ? Sh::kHalfRows : Sh::kRingRows);
+    if (e_flat && l_flat) {
+      const S* ep = &lds->ring[ENTER ? eb : 0][lane];
+      const S* lp = &lds->ring[LEAVE ? lb : 0][lane];
 #pragma unroll
-    for (int p = 0; p < kChunk; ++p) {
-      if (ENTER) e[p] = enter_val(x0 + p);
-      if (LEAVE) l[p] = leave_val(x0 + p);
+      for (int p = 0; p < kChunk; ++p) {
+        if (ENTER) e[p] = Storage<S>::widen(ep[p * 64]);
+        if (LEAVE) l[p] = Storage<S>::widen(lp[p * 64]);
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < kChunk; ++p) {
+        if (ENTER) e[p] = enter_val(x0 + p);
+        if (LEAVE) l[p] = leave_val(x0 + p);
+      }
     }
     const float m_const = kConstMult ? __int_as_float(__builtin_amdgcn_readfirstlane(mult_bits)) : 0.0f;
 #pragma unroll
@@ -819,11 +862,11 @@ struct RingLine {
 
 // Lines line0 .. line0 + 64/DP - 1 of a staged blur pass (those below w),
 // by one wave.
-template <typename S, int DP>
+template <typename S, int DP, int RR>
 __device__ __forceinline__ void blur_staged_line(const S* __restrict__ in, S* __restrict__ out, int w, int r,
-                                                 int vertical, int64_t line0, int lane, RingLds<S>* lds) {
-  using Sh = RingShape<S>;
-  using L_t = RingLine<S, DP>;
+                                                 int vertical, int64_t line0, int lane, RingLds<S, RR>* lds) {
+  using Sh = RingShape<S, RR>;
+  using L_t = RingLine<S, DP, RR>;
   L_t L;
   // Element offset of line l at position 0, and between positions.
   auto line_off = [&](int64_t l) { return vertical ? l * DP : l * w * DP; };
@@ -850,7 +893,7 @@ __device__ __forceinline__ void blur_staged_line(const S* __restrict__ in, S* __
   L.n_chunks = (w + Sh::kChunk - 1) / Sh::kChunk;
   L.ahead = (r + Sh::kChunk - 1) / Sh::kChunk;
   L.n_steps = L.ahead + L.n_chunks;
-  L.split = !ring_leave<S>(r);
+  L.split = !ring_leave<S, RR>(r);
   // Step e sums outputs of chunk k = e - A, whose leaving positions reach
   // up to k kChunk + kChunk - 2 - r: chunk e - lag.
   L.lag = L.ahead - ((Sh::kChunk - 2 - r) >= 0 ? (Sh::kChunk - 2 - r) / Sh::kChunk
@@ -864,25 +907,26 @@ __device__ __forceinline__ void blur_staged_line(const S* __restrict__ in, S* __
 // One group of 64/DP lines per wave, WPB waves per block: block `bid` of
 // `nblocks` takes groups bid * WPB + wave, and walks on with a stride if
 // there are more groups than waves.
-template <typename S, int DP, int WPB>
+template <typename S, int DP, int WPB, int RR>
 __device__ __forceinline__ void blur_staged_lines(const S* __restrict__ in, S* __restrict__ out, int w, int r,
-                                                  int vertical, int64_t bid, int64_t nblocks, RingLds<S>* stage) {
+                                                  int vertical, int64_t bid, int64_t nblocks, RingLds<S, RR>* stage) {
   constexpr int kLinesPerWave = 64 / DP;
   const int wib = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   for (int64_t g = bid * WPB + wib; g * kLinesPerWave < w; g += nblocks * WPB)
-    blur_staged_line<S, DP>(in, out, w, r, vertical, g * kLinesPerWave, lane, stage + wib);
+    blur_staged_line<S, DP, RR>(in, out, w, r, vertical, g * kLinesPerWave, lane, stage + wib);
 }
 
-// Staged blur pass for cells of at least 16 bytes (DP * sizeof(S) >= 16).
-template <typename S, int DP, int WPB>
+// Staged blur pass for cells of at least 16 bytes (DP * sizeof(S) >= 16),
+// with a ring of RR rows per wave.
+template <typename S, int DP, int WPB, int RR>
 __global__ __launch_bounds__(WPB * 64) void k_blur_staged(const S* __restrict__ in, S* __restrict__ out, int w,
                                                           const DevState* __restrict__ st, int radius,
                                                           int vertical, int32_t* __restrict__ table) {
-  __shared__ RingLds<S> s_stage[WPB];
+  __shared__ RingLds<S, RR> s_stage[WPB];
   int r;
   if (!pass_radius(st, radius, r)) return;
-  blur_staged_lines<S, DP, WPB>(in, out, w, r, vertical, blockIdx.x, gridDim.x, s_stage);
+  blur_staged_lines<S, DP, WPB, RR>(in, out, w, r, vertical, blockIdx.x, gridDim.x, s_stage);
   if (table != nullptr) fill_group_table<WPB * 64>(table, st->beta, st->keys, blockIdx.x, gridDim.x);
 }
 
@@ -892,6 +936,10 @@ template <typename S, int DP>
 constexpr bool staged_cells() {
   return DP * static_cast<int>(sizeof(S)) >= 16;
 }
+
+// float32 waves of a staged pass with the 128-row ring (37 KB of LDS each)
+// that fit on the chip at once: 4 per CU, 256 CUs.
+constexpr int64_t kStagedWavesAtLargeRing = 1024;
 
 // Wave groups (of 64/DP lines) of a staged pass over w lines.
 template <int DP>
@@ -1273,16 +1321,17 @@ __device__ __forceinline__ void assign_items(S* __restrict__ G, const S* __restr
         __hip_atomic_fetch_add(&st->energy_acc[slot_acc], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned long long m_old =
         __hip_atomic_fetch_add(&st->moved_acc[slot_acc], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // Wait for both results: once they have returned, both additions have
-    // been made where every block's atomics meet, before anything this
-    // thread does next (the control step's ticket).
-    asm volatile("" : : "v"(e_old), "v"(m_old) : "memory");
+    // Wait for both results (and every earlier memory operation of this
+    // wave): once they have returned, both additions have been made where
+    // every block's atomics meet, before anything this thread does next
+    // (the control step's ticket).
+    asm volatile("s_waitcnt vmcnt(0)" : : "v"(e_old), "v"(m_old) : "memory");
   }
 }
 
-// The control step at the end of a reorder's assignment (defined with the
-// controller below).
-template <int NT>
+// The preparation and the control step of a reorder's assignment (defined
+// with the controller below).
+__device__ void prepare_step(DevState* __restrict__ st, const LevelInfo* __restrict__ levels);
 __device__ void reorder_done(DevState* __restrict__ st, const LevelInfo* __restrict__ levels,
                              plas_level_out* __restrict__ trace, uint32_t nblocks);
 
@@ -1307,8 +1356,9 @@ void k_assign(S* __restrict__ G, const S* __restrict__ T, int32_t* __restrict__ 
               const int32_t* __restrict__ table, DevState* __restrict__ st,
               const LevelInfo* __restrict__ levels, plas_level_out* __restrict__ trace, int control) {
   if (st->done) return;
+  if (control && blockIdx.x == 0 && threadIdx.x == 0) prepare_step(st, levels);
   assign_items<DP, S>(G, T, P, table, st, blockIdx.x, gridDim.x);
-  if (control) reorder_done<kBlock>(st, levels, trace, gridDim.x);
+  if (control && threadIdx.x < 64) reorder_done(st, levels, trace, gridDim.x);
 }
 
 // ----------------------------------------------------------------- energy
@@ -1406,11 +1456,11 @@ __global__ __launch_bounds__(kBlock) void k_vad_finish(const double* __restrict_
 // E is compared with the previous energy; an improvement of at least
 // ceil(E_prev / M) keeps the level and its block shift; the first stall
 // draws a new shift; a stall right after a new shift ends the level
-// (phi <- decay * phi, precomputed in `levels`). `shift` is block shift
-// number st.j and `keys` the grouping keys of reorder st.k + 1, both drawn
-// beforehand (they do not depend on E). trace may be NULL.
+// (phi <- decay * phi, precomputed in `levels`). The block shift number
+// st.j, the grouping keys of reorder st.k + 1 and the next level come
+// prepared in st.next_* (none depends on E). trace may be NULL.
 __device__ void control_step(DevState& st, const LevelInfo* __restrict__ levels,
-                             plas_level_out* __restrict__ trace, const int32_t shift[2], const uint64_t keys[4]) {
+                             plas_level_out* __restrict__ trace) {
   unsigned long long E = 0, moved = 0;
   for (int i = 0; i < kAccSlots; ++i) {
     E += st.energy_acc[i];
@@ -1447,7 +1497,7 @@ __device__ void control_step(DevState& st, const LevelInfo* __restrict__ levels,
       st.done = 1;
       st.ended = 1;
     } else {
-      const LevelInfo lv = levels[next];
+      const LevelInfo lv = st.next_level;
       st.level = next;
       st.r = lv.r;
       st.beta = lv.beta;
@@ -1455,8 +1505,8 @@ __device__ void control_step(DevState& st, const LevelInfo* __restrict__ levels,
       st.groups_per_block = lv.groups_per_block;
       st.groups = lv.groups;
       st.singles = lv.singles;
-      st.dy = shift[0];
-      st.dx = shift[1];
+      st.dy = st.next_dy;
+      st.dx = st.next_dx;
       st.j += 1;
       st.has_prev = 0;
       st.just_shifted = 0;
@@ -1464,59 +1514,72 @@ __device__ void control_step(DevState& st, const LevelInfo* __restrict__ levels,
       st.level_moved = 0;
     }
   } else {
-    st.dy = shift[0];
-    st.dx = shift[1];
+    st.dy = st.next_dy;
+    st.dx = st.next_dx;
     st.j += 1;
     st.just_shifted = 1;
     st.energy_prev = E;
   }
   if (st.max_reorders > 0 && st.k >= st.max_reorders) st.done = 1;
   if (!st.done)
-    for (int i = 0; i < 4; ++i) st.keys[i] = keys[i];
+    for (int i = 0; i < 4; ++i) st.keys[i] = st.next_keys[i];
 }
 
-// The end of a reorder's assignment launch, run by every block after it has
-// added its sums to the state (NT threads per block, nblocks blocks of this
-// sort). Each block takes a ticket (an atomic increment, made after its sums
-// have been added); the one that draws the last ticket sees every block's
-// sums and runs the control step on the state in place: no block of the
-// launch reads the state after taking its ticket, and the next launch of the
-// sort starts after this one ends. Device-scope fences are not needed and
-// would be costly here (each writes back the L2 of its chiplet): the sums,
-// the tickets and the last block's reads are all device-scope atomics. The
-// two random draws the step may use run at the same time on two other
-// waves.
-template <int NT>
+// What the control step of the running reorder may need, prepared by one
+// thread of the assignment's first block before its items: block shift
+// number j, the grouping keys of reorder k + 1, the next level. Written
+// with device-scope atomic exchanges, made where every block's atomics meet
+// and complete (their results returned) before that thread takes its
+// block's ticket, so the last block, which reads the state after every
+// ticket, sees them.
+__device__ void prepare_step(DevState* __restrict__ st, const LevelInfo* __restrict__ levels) {
+  int32_t dy, dx;
+  block_shift(st->seed, st->j, st->w, &dy, &dx);
+  const Words4 keys = draw(st->seed, kDrawGrouping, static_cast<uint64_t>(st->k + 1));
+  __hip_atomic_exchange(&st->next_dy, dy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_exchange(&st->next_dx, dx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int i = 0; i < 4; ++i)
+    __hip_atomic_exchange(&st->next_keys[i], keys.v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int next = st->level + 1;
+  if (next < st->nlevels) {
+    static_assert(sizeof(LevelInfo) % 4 == 0, "level copied as 32-bit words");
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(levels + next);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&st->next_level);
+    for (int i = 0; i < static_cast<int>(sizeof(LevelInfo) / 4); ++i)
+      __hip_atomic_exchange(dst + i, src[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// The end of a reorder's assignment launch, run by the first wave of every
+// block after the block has added its sums to the state (nblocks blocks of
+// this sort; the block's other waves have ended). Its first thread takes a
+// ticket (an atomic increment, made after the sums were added); the wave
+// that draws the last ticket sees every block's sums and runs the control
+// step on the state in place: no block of the launch reads the state after
+// taking its ticket, and the next launch of the sort starts after this one
+// ends. Device-scope fences are not needed and would be costly here (each
+// writes back the L2 of its chiplet): the sums, the tickets, the prepared
+// values and the last wave's reads are all device-scope atomics.
 __device__ void reorder_done(DevState* __restrict__ st, const LevelInfo* __restrict__ levels,
                              plas_level_out* __restrict__ trace, uint32_t nblocks) {
-  static_assert(NT >= 192, "the draws run on the second and third waves");
   static_assert(sizeof(DevState) % 4 == 0, "state is copied as 32-bit words");
   constexpr int kWords = sizeof(DevState) / 4;
   __shared__ DevState s_st;
-  __shared__ uint32_t s_last;
-  __shared__ int32_t s_shift[2];
-  __shared__ uint64_t s_keys[4];
-  if (threadIdx.x == 0)
-    s_last = __hip_atomic_fetch_add(&st->blocks_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nblocks - 1
-                 ? 1u
-                 : 0u;
-  __syncthreads();
-  if (s_last == 0) return;
+  const int lane = threadIdx.x & 63;
+  uint32_t last = 0;
+  if (lane == 0)
+    last = __hip_atomic_fetch_add(&st->blocks_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nblocks - 1
+               ? 1u
+               : 0u;
+  if (__builtin_amdgcn_readfirstlane(last) == 0) return;
   uint32_t* words = reinterpret_cast<uint32_t*>(&s_st);
   uint32_t* gwords = reinterpret_cast<uint32_t*>(st);
-  for (int i = threadIdx.x; i < kWords; i += NT)
+  for (int i = lane; i < kWords; i += 64)
     words[i] = __hip_atomic_load(gwords + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  if (threadIdx.x == 64) {
-    block_shift(s_st.seed, s_st.j, s_st.w, &s_shift[0], &s_shift[1]);
-  } else if (threadIdx.x == 128) {
-    const Words4 k = draw(s_st.seed, kDrawGrouping, static_cast<uint64_t>(s_st.k + 1));
-    for (int i = 0; i < 4; ++i) s_keys[i] = k.v[i];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) control_step(s_st, levels, trace, s_shift, s_keys);
-  __syncthreads();
-  for (int i = threadIdx.x; i < kWords; i += NT) gwords[i] = words[i];
+  wave_lds_sync();
+  if (lane == 0) control_step(s_st, levels, trace);
+  wave_lds_sync();
+  for (int i = lane; i < kWords; i += 64) gwords[i] = words[i];
 }
 
 // ------------------------------------------------------------------ batch
@@ -1574,10 +1637,14 @@ __device__ __forceinline__ S* route_grid(const BatchGridView& g, int sel) {
   return global_ptr<S>(sel == 0 ? g.G : sel == 1 ? g.H : g.T);
 }
 
+// Ring rows of the batched staged pass (grids of a batch take whole lines
+// by the thousand; the larger ring keeps leaving values on chip up to r = 47).
+constexpr int kBatchRingRows = 128;
+
 template <typename S, int DP, int WPB>
 __global__ __launch_bounds__(WPB * 64) void k_blur_staged_batch(const BatchGrid* __restrict__ grids,
                                                                 const uint32_t* __restrict__ map, int route) {
-  __shared__ RingLds<S> s_stage[WPB];
+  __shared__ RingLds<S, kBatchRingRows> s_stage[WPB];
   uint32_t local;
   const BatchGridView& g = batch_grid(grids, map, local);
   const DevState* st = global_ptr<const DevState>(g.state);
@@ -1586,7 +1653,7 @@ __global__ __launch_bounds__(WPB * 64) void k_blur_staged_batch(const BatchGrid*
   const int vertical = route_vertical(route);
   const S* in = route_grid<S>(g, (route >> 1) & 3);
   S* out = route_grid<S>(g, (route >> 3) & 3);
-  blur_staged_lines<S, DP, WPB>(in, out, g.w, r, vertical, local, g.blur_blocks, s_stage);
+  blur_staged_lines<S, DP, WPB, kBatchRingRows>(in, out, g.w, r, vertical, local, g.blur_blocks, s_stage);
   if (route_table(route))
     fill_group_table<WPB * 64>(global_ptr<int32_t>(g.table), st->beta, st->keys, local, g.blur_blocks);
 }
@@ -1617,10 +1684,12 @@ void k_assign_batch(const BatchGrid* __restrict__ grids, const uint32_t* __restr
   const BatchGridView& g = batch_grid(grids, map, local);
   DevState* st = global_ptr<DevState>(g.state);
   if (st->done) return;
+  if (local == 0 && threadIdx.x == 0) prepare_step(st, global_ptr<const LevelInfo>(g.levels));
   assign_items<DP, S>(global_ptr<S>(g.G), global_ptr<const S>(g.T), global_ptr<int32_t>(g.P),
                       global_ptr<const int32_t>(g.table), st, local, g.assign_blocks);
-  reorder_done<kBlock>(st, global_ptr<const LevelInfo>(g.levels), global_ptr<plas_level_out>(g.trace),
-                       static_cast<uint32_t>(g.assign_blocks));
+  if (threadIdx.x < 64)
+    reorder_done(st, global_ptr<const LevelInfo>(g.levels), global_ptr<plas_level_out>(g.trace),
+                 static_cast<uint32_t>(g.assign_blocks));
 }
 
 // (done, k) of each listed sort's state, for the host's check between
@@ -1795,9 +1864,16 @@ hipError_t blur_pass_dp(const void* in, void* out, int w, const DevState* st, in
   };
   if constexpr (staged_cells<S, DP>()) {
     constexpr int kThreads = kBlurWavesPerBlock * 64;
-    const int blocks = with_table((staged_groups<DP>(w) + kBlurWavesPerBlock - 1) / kBlurWavesPerBlock, kThreads);
-    k_blur_staged<S, DP, kBlurWavesPerBlock><<<blocks, kThreads, 0, stream>>>(
-        static_cast<const S*>(in), static_cast<S*>(out), w, st, radius, vertical, ta.table);
+    const int64_t groups = staged_groups<DP>(w);
+    const int blocks = with_table((groups + kBlurWavesPerBlock - 1) / kBlurWavesPerBlock, kThreads);
+    // The 128-row ring while every wave of the pass fits on the chip at
+    // once with it (4 float32 waves per CU), else the 64-row ring (8 per CU).
+    if (sizeof(S) == 2 || groups <= kStagedWavesAtLargeRing)
+      k_blur_staged<S, DP, kBlurWavesPerBlock, 128><<<blocks, kThreads, 0, stream>>>(
+          static_cast<const S*>(in), static_cast<S*>(out), w, st, radius, vertical, ta.table);
+    else
+      k_blur_staged<S, DP, kBlurWavesPerBlock, 64><<<blocks, kThreads, 0, stream>>>(
+          static_cast<const S*>(in), static_cast<S*>(out), w, st, radius, vertical, ta.table);
   } else {
     const int blocks = with_table((blur_reg_waves<DP>(w) + kWavesPerBlock - 1) / kWavesPerBlock, kBlock);
     k_blur<DP, S><<<blocks, kBlock, 0, stream>>>(static_cast<const S*>(in), static_cast<S*>(out), w, st, radius,
