@@ -460,13 +460,14 @@ __global__ __launch_bounds__(kBlock) void k_blur(const S* __restrict__ in, S* __
   if (table != nullptr) fill_group_table<kBlock>(table, st->beta, st->keys, blockIdx.x, gridDim.x);
 }
 
-// Streaming (non-temporal) cache hints, measured on the 1024^2 float32 and
-// 1448^2 bfloat16 sorts. The blur's outputs are not read again before they
-// leave the cache, and the assignment reads
-// every cell of G and T once per reorder: with these hints dirty blur output
-// no longer competes with the assignment's random reads (assignment 127 ->
-// 102 us at 1024^2 float32, whole sort -6 %).
-constexpr bool kBlurStreamStores = true;
+// Cache hints, measured on the 1024^2 float32 sort. The assignment reads
+// every cell of G and T once per reorder, in random group order: streaming
+// (non-temporal) loads keep those reads from evicting what the next blur pass
+// reads (with normal loads the assignment took 109 -> 132 us). The staged
+// blur stores its lines normally: the next kernel reads them soon after, and
+// streaming stores made the whole sort 3.7 % slower (blur 108 -> 113 us per
+// pass, assignment 109 -> 111 us).
+constexpr bool kBlurStreamStores = false;
 constexpr bool kAssignStreamLoads = true;
 
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
