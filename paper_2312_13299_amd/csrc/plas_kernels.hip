@@ -529,8 +529,10 @@ __device__ __forceinline__ Q load_quad(const Q* p) {
 // then, from step A = ceil(r / kChunk) on, the outputs x of chunk e - A (x + r
 // lies in chunk e or e - 1). While the ring also holds every leaving position
 // x - r - 1 still to come beside the chunks in flight, leaving values are read
-// back from it; otherwise the ring is split in two halves and a second stream
-// loads the leaving chunks (the same positions again) into the upper half.
+// back from it; otherwise the ring is split in two halves and the leaving
+// chunks reach the upper half from registers (float32, up to 24 chunks back:
+// 48 <= r <= 192), where each chunk was kept since it entered, or from a
+// second load stream (the same positions again).
 // Loads are issued at positions clamped into the line (a clamped load fetches
 // a value the sums never use), so every chunk is exactly kVec load
 // instructions.
@@ -563,6 +565,14 @@ struct RingShape {
   static constexpr bool kEarly = PLAS_BLUR_EARLY;  // a step issues its loads before summing (else after)
   static constexpr int kRingRows = RR;
   static constexpr int kSlots = kRingRows / kChunk;
+  // Chunks a wave keeps in registers for the leaving values: 24 float32
+  // chunks with the 128-row ring (384 registers; one wave per SIMD, as the
+  // ring's LDS allows). bfloat16 passes run two waves per SIMD and keep the
+  // second load stream: with 16 chunks in registers they measured no faster
+  // (1448^2, r = 48..128: 146 / 144 us per row / column pass, against
+  // 138 / 148 us).
+  static constexpr int kRegChunks = RR >= 128 && sizeof(S) == 4 ? 24 : 0;
+  static constexpr int kRegWords = kChunk * static_cast<int>(sizeof(S)) / 4;  // registers per chunk
   static constexpr int kHalfRows = kRingRows / 2;  // rows of each stream when the ring is split
   static_assert(kRingRows % kChunk == 0 && (kRingRows & (kRingRows - 1)) == 0, "ring shape");
   static_assert(kHalfRows / kChunk >= kDepth + (kEarly ? 1 : 0), "a split half holds the chunks in use and in flight");
@@ -571,7 +581,7 @@ struct RingShape {
 // LDS of one wave: (RR + 16) rows of 256 B (float32) or 128 B (bfloat16),
 // 36 KB / 18 KB with the 128-row ring.
 template <typename S, int RR>
-struct RingLds {
+struct alignas(16) RingLds {
   S ring[RingShape<S, RR>::kRingRows][64];
   S out[RingShape<S, RR>::kChunk][64];
 };
@@ -665,7 +675,8 @@ struct RingLine {
   int lag;       // the leaving chunk needed at step e is e - lag (split ring)
   int n_steps;   // A + M
   int q, j, lane;
-  bool split;        // the leaving values have their own stream (the ring's upper half)
+  bool split;        // the leaving values have their own region (the ring's upper half)
+  bool regs;         // split, and the leaving chunks come from registers instead of a second load stream
   int enter_mask;    // ring rows of the entering stream - 1
   uint32_t ring_m0;  // LDS byte address of ring row 0 (the same for all lanes)
   RingLds<S, RR>* lds;
@@ -691,7 +702,9 @@ struct RingLine {
 
   // Issue slot u: entering chunk u and, when split, leaving chunk u - lag.
   __device__ __forceinline__ bool slot_enter(int u) const { return u < n_chunks; }
-  __device__ __forceinline__ bool slot_leave(int u) const { return split && u - lag >= 0 && u - lag < n_chunks; }
+  __device__ __forceinline__ bool slot_leave(int u) const {
+    return split && !regs && u - lag >= 0 && u - lag < n_chunks;
+  }
   __device__ __forceinline__ void issue(int u) const {
     if (slot_enter(u)) load_chunk<kBlurEnterStream>(u, (u * kChunk) & enter_mask);
     if (slot_leave(u))
@@ -848,7 +861,80 @@ struct RingLine {
     }
   }
 
+  // Register ring of the leaving values: step e reads chunk e back from the
+  // entering half and swaps it with register slot e mod lag, which holds
+  // chunk e - lag, the newest leaving chunk of the step; that chunk goes to
+  // its rows of the leaving half. A chunk is used as leaving values at steps
+  // e and e + 1 only, and the leaving half holds four. A chunk's kChunk rows
+  // are contiguous in both halves, so it moves as 16-byte pieces (lane l
+  // holds bytes 16 l .. of each KB) in whatever order: only its place in the
+  // leaving half matters. Past the last chunk the rows read are stale; what
+  // they push is never popped (a chunk pushed at step e >= M would pop at
+  // e + lag >= M + A, after the last step).
+  using Word = uint32_t;
+  static constexpr int kWords = Sh::kRegWords;  // per lane and chunk
+  static constexpr int kPieces = kWords / 4;    // 16-byte pieces per lane and chunk
+  template <int K>
+  __device__ __forceinline__ void exchange(Word (&keep)[K][kWords], int slot, int e) const {
+    Word in[kWords], out[kWords];
+    const char* ep = reinterpret_cast<const char*>(&lds->ring[(e * kChunk) & enter_mask][0]) + 16 * lane;
+#pragma unroll
+    for (int i = 0; i < kPieces; ++i) {
+      const uint4 v = *reinterpret_cast<const uint4*>(ep + 1024 * i);
+      in[4 * i] = v.x;
+      in[4 * i + 1] = v.y;
+      in[4 * i + 2] = v.z;
+      in[4 * i + 3] = v.w;
+    }
+    // The uniform slot is found in two levels of scalar branches: its group
+    // of kGroup slots, then the slot.
+    constexpr int kGroup = 6;
+#pragma unroll
+    for (int g = 0; g < K; g += kGroup) {
+      if (slot >= g && slot < g + kGroup) {
+#pragma unroll
+        for (int k = g; k < g + kGroup && k < K; ++k) {
+          if (k == slot) {
+#pragma unroll
+            for (int p = 0; p < kWords; ++p) {
+              out[p] = keep[k][p];
+              keep[k][p] = in[p];
+            }
+          }
+        }
+      }
+    }
+    if (e >= lag) {
+      char* lp = reinterpret_cast<char*>(&lds->ring[Sh::kHalfRows + (((e - lag) * kChunk) & (Sh::kHalfRows - 1))][0]) +
+                 16 * lane;
+#pragma unroll
+      for (int i = 0; i < kPieces; ++i)
+        *reinterpret_cast<uint4*>(lp + 1024 * i) = make_uint4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
+    }
+  }
+
+  __device__ __forceinline__ void run_regs() const {
+    if constexpr (Sh::kRegChunks > 0) {
+      Word keep[Sh::kRegChunks][kWords];
+      for (int u = 0; u <= Sh::kDepth - 2; ++u) issue(u);
+      float s = 0.0f;
+      int slot = 0;
+      for (int e = 0; e < n_steps; ++e) {
+        if (slot_loads(e) > 0) wait_vm_dyn(ops_after(e));
+        exchange<Sh::kRegChunks>(keep, slot, e);
+        if (e * kChunk <= first_hi) start_sum(e, s);
+        if (e >= ahead) outputs(e - ahead, s);
+        issue(e + Sh::kDepth - 1);
+        slot = slot + 1 == lag ? 0 : slot + 1;
+      }
+    }
+  }
+
   __device__ __forceinline__ void run() const {
+    if (regs) {
+      run_regs();
+      return;
+    }
     for (int u = 0; u <= Sh::kDepth - 2; ++u) issue(u);
     float s = 0.0f;
     for (int e = 0; e < n_steps; ++e) {
@@ -899,10 +985,18 @@ __device__ __forceinline__ void blur_staged_line(const S* __restrict__ in, S* __
   // up to k kChunk + kChunk - 2 - r: chunk e - lag.
   L.lag = L.ahead - ((Sh::kChunk - 2 - r) >= 0 ? (Sh::kChunk - 2 - r) / Sh::kChunk
                                                : -((r - Sh::kChunk + 2 + Sh::kChunk - 1) / Sh::kChunk));
+  L.regs = L.split && L.lag <= Sh::kRegChunks;
   L.enter_mask = (L.split ? Sh::kHalfRows : Sh::kRingRows) - 1;
   L.ring_m0 = __builtin_amdgcn_readfirstlane(
       static_cast<uint32_t>(reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) S*)(&lds->ring[0][0]))));
   L.run();
+}
+
+// Waves per SIMD a staged kernel keeps room for in registers: one float32
+// wave with the 128-row ring (its LDS allows no more), else two.
+template <typename S, int RR>
+constexpr int staged_waves_per_eu() {
+  return sizeof(S) == 4 && RR >= 128 ? 1 : 2;
 }
 
 // One group of 64/DP lines per wave, WPB waves per block: block `bid` of
@@ -921,9 +1015,9 @@ __device__ __forceinline__ void blur_staged_lines(const S* __restrict__ in, S* _
 // Staged blur pass for cells of at least 16 bytes (DP * sizeof(S) >= 16),
 // with a ring of RR rows per wave.
 template <typename S, int DP, int WPB, int RR>
-__global__ __launch_bounds__(WPB * 64) void k_blur_staged(const S* __restrict__ in, S* __restrict__ out, int w,
-                                                          const DevState* __restrict__ st, int radius,
-                                                          int vertical, int32_t* __restrict__ table) {
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(staged_waves_per_eu<S, RR>())))
+void k_blur_staged(const S* __restrict__ in, S* __restrict__ out, int w, const DevState* __restrict__ st, int radius,
+                   int vertical, int32_t* __restrict__ table) {
   __shared__ RingLds<S, RR> s_stage[WPB];
   int r;
   if (!pass_radius(st, radius, r)) return;
@@ -1643,8 +1737,8 @@ __device__ __forceinline__ S* route_grid(const BatchGridView& g, int sel) {
 constexpr int kBatchRingRows = 128;
 
 template <typename S, int DP, int WPB>
-__global__ __launch_bounds__(WPB * 64) void k_blur_staged_batch(const BatchGrid* __restrict__ grids,
-                                                                const uint32_t* __restrict__ map, int route) {
+__global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(staged_waves_per_eu<S, kBatchRingRows>())))
+void k_blur_staged_batch(const BatchGrid* __restrict__ grids, const uint32_t* __restrict__ map, int route) {
   __shared__ RingLds<S, kBatchRingRows> s_stage[WPB];
   uint32_t local;
   const BatchGridView& g = batch_grid(grids, map, local);

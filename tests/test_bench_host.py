@@ -81,9 +81,13 @@ def test_percentile_nearest_rank():
 def test_cpu_baseline_on_a_small_grid():
     import synthetic
     F = synthetic.gaussian_attributes(64 * 64, 1)
-    b = bench.cpu_baseline(F, 64, 0x5EED, 400, 24)
+    trace = [(phi, 6) for phi in (31.0, 20.0, 9.0, 4.0, 2.0, 1.0)]
+    b = bench.cpu_baseline(F, 64, 0x5EED, trace, 24)
     assert b["kind"] == "oracle" and b["unit"] == "Gaussians/s" and b["cores"] >= 1
-    assert b["value"] > 0 and "stopped after 24 reorders" in b["sample"]
+    assert b["value"] > 0 and "24 reorders in" in b["sample"] and "for the 36 reorders" in b["sample"]
+    # Bands of levels 0-0, 1-2, 3-3, 4-5 start at their middle levels.
+    for phi in ("31.0", "20.0", "4.0", "2.0"):
+        assert f"phi {phi}:" in b["sample"]
     assert b["one_thread"]["sample_reorders"] == 2 and b["one_thread"]["seconds_per_reorder"] > 0
 
 

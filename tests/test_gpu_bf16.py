@@ -22,7 +22,11 @@ def _bf16(torch, x):
 
 
 @pytest.mark.parametrize("side,d,r", [(7, 3, 2), (17, 14, 5), (33, 59, 7), (64, 59, 31), (100, 3, 9),
-                                      (256, 59, 127), (250, 8, 300)])
+                                      (256, 59, 127), (250, 8, 300),
+                                      # radii whose leaving values a wave keeps in
+                                      # registers (48..128), both ends, one past
+                                      (97, 59, 48), (301, 59, 128), (301, 59, 129), (1000, 59, 100),
+                                      (150, 32, 75), (77, 8, 60)])
 def test_blur_bf16_bitwise(env, side, d, r):
     torch, plas, ctx, ref = env
     rng = np.random.default_rng(side + d + r)

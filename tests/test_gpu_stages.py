@@ -40,6 +40,9 @@ BLUR_CASES = [
     # (side, d, r)
     (2, 1, 1), (3, 3, 1), (5, 2, 0), (7, 3, 2), (16, 4, 3), (17, 14, 5), (33, 59, 7), (33, 59, 40),
     (64, 59, 31), (64, 64, 1), (100, 3, 9), (129, 16, 63), (256, 59, 127), (250, 8, 300),
+    # float32 radii whose leaving values a wave keeps in registers (48..192),
+    # both ends, and the first radius past them.
+    (97, 59, 48), (301, 59, 192), (301, 59, 193), (1024, 59, 100), (150, 32, 75), (77, 4, 60),
 ]
 
 
