@@ -69,6 +69,7 @@ struct Launch {
   int dp;
   int storage;
   int wpb;
+  int regs;        // blur: leaving values in registers (plas::blur_register_ring)
   size_t map_off;  // byte offset of the block map in the plan
   int blocks;
 };
@@ -97,6 +98,7 @@ struct Sort {
 // Lines per block of a sort's blur launches (0 for the register kernel,
 // which has one fixed shape).
 int blur_wpb(const Sort& s) { return plas::staged_blur(s.dp, s.storage) ? s.wpb : 0; }
+int blur_regs(const Sort& s) { return plas::blur_register_ring(s.w, s.dp, s.storage) ? 1 : 0; }
 
 }  // namespace
 
@@ -470,7 +472,7 @@ class BatchRun {
     off = align_up(off + run_list_.size() * sizeof(int32_t));
     launches_.clear();
     std::vector<std::vector<uint32_t>> maps;
-    auto add_launch = [&](int kind, int dp, int storage, int wpb, const std::vector<int>& members) {
+    auto add_launch = [&](int kind, int dp, int storage, int wpb, int regs, const std::vector<int>& members) {
       std::vector<uint32_t> map;
       for (int slot : members) {
         const plas::BatchGrid& g = sorts_[slot].grid;
@@ -478,27 +480,27 @@ class BatchRun {
         for (int b = 0; b < nb; ++b) map.push_back((static_cast<uint32_t>(slot) << 16) | static_cast<uint32_t>(b));
       }
       if (map.empty()) return;
-      Launch L{kind, dp, storage, wpb, off, static_cast<int>(map.size())};
+      Launch L{kind, dp, storage, wpb, regs, off, static_cast<int>(map.size())};
       off = align_up(off + map.size() * sizeof(uint32_t));
       launches_.push_back(L);
       maps.push_back(std::move(map));
     };
-    // Blur launches per (dp, storage, lines per block); assignment per (dp, storage).
+    // Blur launches per (dp, storage, lines per block, register slots);
+    // assignment per (dp, storage).
     for (int pass = 0; pass < 2; ++pass) {
-      std::vector<std::array<int, 3>> keys;
+      std::vector<std::array<int, 4>> keys;
+      auto key_of = [&](const Sort& s) -> std::array<int, 4> {
+        return {s.dp, s.storage, pass == 0 ? blur_wpb(s) : 0, pass == 0 ? blur_regs(s) : 0};
+      };
       for (int slot : run_list_) {
-        const Sort& s = sorts_[slot];
-        const std::array<int, 3> k = {s.dp, s.storage, pass == 0 ? blur_wpb(s) : 0};
+        const std::array<int, 4> k = key_of(sorts_[slot]);
         if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
       }
       for (const auto& k : keys) {
         std::vector<int> members;
-        for (int slot : run_list_) {
-          const Sort& s = sorts_[slot];
-          if (s.dp == k[0] && s.storage == k[1] && (pass == 1 || blur_wpb(s) == k[2]))
-            members.push_back(slot);
-        }
-        add_launch(pass == 0 ? kBlur : kAssign, k[0], k[1], k[2], members);
+        for (int slot : run_list_)
+          if (key_of(sorts_[slot]) == k) members.push_back(slot);
+        add_launch(pass == 0 ? kBlur : kAssign, k[0], k[1], k[2], k[3], members);
       }
     }
     const size_t bytes = off;
@@ -545,7 +547,7 @@ class BatchRun {
         for (const Launch& L : launches_)
           if (L.kind == kBlur)
             PLAS_HIP(h_, plas::launch_blur_batch(grids, map_of(L), L.blocks, L.dp, L.storage, L.wpb == 0 ? 4 : L.wpb,
-                                                 route, stream));
+                                                 route, L.regs, stream));
       if (timed) PLAS_HIP(h_, hipEventRecord(b_->events[3 * i + 1], stream));
       for (const Launch& L : launches_)
         if (L.kind == kAssign)

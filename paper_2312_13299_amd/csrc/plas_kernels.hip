@@ -460,14 +460,20 @@ __global__ __launch_bounds__(kBlock) void k_blur(const S* __restrict__ in, S* __
   if (table != nullptr) fill_group_table<kBlock>(table, st->beta, st->keys, blockIdx.x, gridDim.x);
 }
 
-// Cache hints, measured on the 1024^2 float32 sort. The assignment reads
-// every cell of G and T once per reorder, in random group order: streaming
-// (non-temporal) loads keep those reads from evicting what the next blur pass
-// reads (with normal loads the assignment took 109 -> 132 us). The staged
-// blur stores its lines normally: the next kernel reads them soon after, and
-// streaming stores made the whole sort 3.7 % slower (blur 108 -> 113 us per
-// pass, assignment 109 -> 111 us).
-constexpr bool kBlurStreamStores = false;
+// Cache hints, measured on whole sorts. The assignment reads every cell of G
+// and T once per reorder, in random group order: streaming (non-temporal)
+// loads keep those reads from evicting what the next blur pass reads (1024^2
+// float32 with normal loads: assignment 109 -> 132 us). The staged blur
+// stores its lines normally where the grid is about the size of the 256 MB
+// Infinity Cache (the 128-row ring: 1024^2 float32 and 1448^2 bfloat16
+// grids), as the next kernel reads them soon after: streaming stores made
+// those sorts 3.7 % and 1.4 % slower. float32 grids of more than 1024 lines
+// (the 64-row ring) are twice that size or more; there streaming stores are
+// faster (1448^2: 5568 against 5668 ms; 2091^2: 15.5 against 16.3 s).
+template <int RR>
+constexpr bool blur_stream_stores() {
+  return RR < 128;
+}
 constexpr bool kAssignStreamLoads = true;
 
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
@@ -530,8 +536,9 @@ __device__ __forceinline__ Q load_quad(const Q* p) {
 // lies in chunk e or e - 1). While the ring also holds every leaving position
 // x - r - 1 still to come beside the chunks in flight, leaving values are read
 // back from it; otherwise the ring is split in two halves and the leaving
-// chunks reach the upper half from registers (float32, up to 24 chunks back:
-// 48 <= r <= 192), where each chunk was kept since it entered, or from a
+// chunks reach the upper half from registers (float32, up to 24 chunks back
+// with the 128-row ring: 48 <= r <= 192; 8 with the 64-row ring:
+// 16 <= r <= 64), where each chunk was kept since it entered, or from a
 // second load stream (the same positions again).
 // Loads are issued at positions clamped into the line (a clamped load fetches
 // a value the sums never use), so every chunk is exactly kVec load
@@ -546,7 +553,7 @@ __device__ __forceinline__ Q load_quad(const Q* p) {
 // compiler does not add its own conservative wait (every load done) before
 // each LDS read; M0 (the LDS base of a load) is set in the same asm statement,
 // and no compiler-generated code of these kernels uses M0.
-template <typename S, int RR>
+template <typename S, int RR, int KR = 0>
 struct RingShape {
   static constexpr int kRowBytes = 64 * static_cast<int>(sizeof(S));  // one position of the wave's lines
   static constexpr int kLanesPerRow = kRowBytes / 16;
@@ -565,16 +572,11 @@ struct RingShape {
   static constexpr bool kEarly = PLAS_BLUR_EARLY;  // a step issues its loads before summing (else after)
   static constexpr int kRingRows = RR;
   static constexpr int kSlots = kRingRows / kChunk;
-  // Chunks a wave keeps in registers for the leaving values: 24 float32
-  // chunks with the 128-row ring (384 registers; one wave per SIMD, as the
-  // ring's LDS allows). bfloat16 passes run two waves per SIMD and keep the
-  // second load stream: with 16 chunks in registers they measured no faster
-  // (1448^2, r = 48..128: 146 / 144 us per row / column pass, against
-  // 138 / 148 us).
-  static constexpr int kRegChunks = RR >= 128 && sizeof(S) == 4 ? 24 : 0;
+  static constexpr int kRegChunks = KR;  // register slots of leaving chunks (0: none)
   static constexpr int kRegWords = kChunk * static_cast<int>(sizeof(S)) / 4;  // registers per chunk
   static constexpr int kHalfRows = kRingRows / 2;  // rows of each stream when the ring is split
   static_assert(kRingRows % kChunk == 0 && (kRingRows & (kRingRows - 1)) == 0, "ring shape");
+  static_assert(KR == 0 || sizeof(S) == 4, "register slots hold float32 chunks");
   static_assert(kHalfRows / kChunk >= kDepth + (kEarly ? 1 : 0), "a split half holds the chunks in use and in flight");
 };
 
@@ -658,9 +660,9 @@ __device__ __forceinline__ void wait_vm_dyn(int n) {
   }
 }
 
-template <typename S, int DP, int RR>
+template <typename S, int DP, int RR, int KR>
 struct RingLine {
-  using Sh = RingShape<S, RR>;
+  using Sh = RingShape<S, RR, KR>;
   static constexpr int kChunk = Sh::kChunk;
   static constexpr int kPiecesPerCell = DP * static_cast<int>(sizeof(S)) / 16;
   static_assert(kPiecesPerCell >= 1, "a cell must hold at least one 16-byte piece");
@@ -856,7 +858,7 @@ struct RingLine {
     for (int i = 0; i < Sh::kVec; ++i) {
       const int x = x0 + Sh::kPos * i + q;
       if (x < w && ld_ok)
-        store16<kBlurStreamStores>(dst + ld_off + static_cast<int64_t>(x) * step,
+        store16<blur_stream_stores<RR>()>(dst + ld_off + static_cast<int64_t>(x) * step,
                                    *reinterpret_cast<const uint4*>(&lds->out[Sh::kPos * i + q][16 / sizeof(S) * j]));
     }
   }
@@ -949,11 +951,11 @@ struct RingLine {
 
 // Lines line0 .. line0 + 64/DP - 1 of a staged blur pass (those below w),
 // by one wave.
-template <typename S, int DP, int RR>
+template <typename S, int DP, int RR, int KR>
 __device__ __forceinline__ void blur_staged_line(const S* __restrict__ in, S* __restrict__ out, int w, int r,
                                                  int vertical, int64_t line0, int lane, RingLds<S, RR>* lds) {
-  using Sh = RingShape<S, RR>;
-  using L_t = RingLine<S, DP, RR>;
+  using Sh = RingShape<S, RR, KR>;
+  using L_t = RingLine<S, DP, RR, KR>;
   L_t L;
   // Element offset of line l at position 0, and between positions.
   auto line_off = [&](int64_t l) { return vertical ? l * DP : l * w * DP; };
@@ -1002,27 +1004,38 @@ constexpr int staged_waves_per_eu() {
 // One group of 64/DP lines per wave, WPB waves per block: block `bid` of
 // `nblocks` takes groups bid * WPB + wave, and walks on with a stride if
 // there are more groups than waves.
-template <typename S, int DP, int WPB, int RR>
+template <typename S, int DP, int WPB, int RR, int KR>
 __device__ __forceinline__ void blur_staged_lines(const S* __restrict__ in, S* __restrict__ out, int w, int r,
                                                   int vertical, int64_t bid, int64_t nblocks, RingLds<S, RR>* stage) {
   constexpr int kLinesPerWave = 64 / DP;
   const int wib = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   for (int64_t g = bid * WPB + wib; g * kLinesPerWave < w; g += nblocks * WPB)
-    blur_staged_line<S, DP, RR>(in, out, w, r, vertical, g * kLinesPerWave, lane, stage + wib);
+    blur_staged_line<S, DP, RR, KR>(in, out, w, r, vertical, g * kLinesPerWave, lane, stage + wib);
 }
 
 // Staged blur pass for cells of at least 16 bytes (DP * sizeof(S) >= 16),
-// with a ring of RR rows per wave.
-template <typename S, int DP, int WPB, int RR>
+// with a ring of RR rows per wave and KR register slots.
+template <typename S, int DP, int WPB, int RR, int KR>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(staged_waves_per_eu<S, RR>())))
 void k_blur_staged(const S* __restrict__ in, S* __restrict__ out, int w, const DevState* __restrict__ st, int radius,
                    int vertical, int32_t* __restrict__ table) {
   __shared__ RingLds<S, RR> s_stage[WPB];
   int r;
   if (!pass_radius(st, radius, r)) return;
-  blur_staged_lines<S, DP, WPB, RR>(in, out, w, r, vertical, blockIdx.x, gridDim.x, s_stage);
+  blur_staged_lines<S, DP, WPB, RR, KR>(in, out, w, r, vertical, blockIdx.x, gridDim.x, s_stage);
   if (table != nullptr) fill_group_table<WPB * 64>(table, st->beta, st->keys, blockIdx.x, gridDim.x);
+}
+
+// Register slots a wave keeps for the leaving values (float32): 24 with the
+// 128-row ring (384 registers; one wave per SIMD, as the ring's LDS allows),
+// 8 with the 64-row ring (128 registers; two waves per SIMD). bfloat16
+// passes run two waves per SIMD and keep the second load stream: with 16
+// slots they measured no faster (1448^2, r = 48..128: 146 / 144 us per
+// row / column pass, against 138 / 148 us).
+template <typename S, int RR>
+constexpr int ring_register_chunks() {
+  return sizeof(S) == 4 ? (RR >= 128 ? 24 : 8) : 0;
 }
 
 // Cells of DP * sizeof(S) bytes are moved in 16-byte pieces when they hold
@@ -1736,7 +1749,7 @@ __device__ __forceinline__ S* route_grid(const BatchGridView& g, int sel) {
 // by the thousand; the larger ring keeps leaving values on chip up to r = 47).
 constexpr int kBatchRingRows = 128;
 
-template <typename S, int DP, int WPB>
+template <typename S, int DP, int WPB, int KR>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(staged_waves_per_eu<S, kBatchRingRows>())))
 void k_blur_staged_batch(const BatchGrid* __restrict__ grids, const uint32_t* __restrict__ map, int route) {
   __shared__ RingLds<S, kBatchRingRows> s_stage[WPB];
@@ -1748,7 +1761,7 @@ void k_blur_staged_batch(const BatchGrid* __restrict__ grids, const uint32_t* __
   const int vertical = route_vertical(route);
   const S* in = route_grid<S>(g, (route >> 1) & 3);
   S* out = route_grid<S>(g, (route >> 3) & 3);
-  blur_staged_lines<S, DP, WPB, kBatchRingRows>(in, out, g.w, r, vertical, local, g.blur_blocks, s_stage);
+  blur_staged_lines<S, DP, WPB, kBatchRingRows, KR>(in, out, g.w, r, vertical, local, g.blur_blocks, s_stage);
   if (route_table(route))
     fill_group_table<WPB * 64>(global_ptr<int32_t>(g.table), st->beta, st->keys, local, g.blur_blocks);
 }
@@ -1962,13 +1975,28 @@ hipError_t blur_pass_dp(const void* in, void* out, int w, const DevState* st, in
     const int64_t groups = staged_groups<DP>(w);
     const int blocks = with_table((groups + kBlurWavesPerBlock - 1) / kBlurWavesPerBlock, kThreads);
     // The 128-row ring while every wave of the pass fits on the chip at
-    // once with it (4 float32 waves per CU), else the 64-row ring (8 per CU).
-    if (sizeof(S) == 2 || groups <= kStagedWavesAtLargeRing)
-      k_blur_staged<S, DP, kBlurWavesPerBlock, 128><<<blocks, kThreads, 0, stream>>>(
-          static_cast<const S*>(in), static_cast<S*>(out), w, st, radius, vertical, ta.table);
-    else
-      k_blur_staged<S, DP, kBlurWavesPerBlock, 64><<<blocks, kThreads, 0, stream>>>(
-          static_cast<const S*>(in), static_cast<S*>(out), w, st, radius, vertical, ta.table);
+    // once with it (4 float32 waves per CU), else the 64-row ring (8 per CU);
+    // register slots for the leaving values on grids the Infinity Cache
+    // does not hold twice over.
+    constexpr int kR128 = ring_register_chunks<S, 128>(), kR64 = ring_register_chunks<S, 64>();
+    const bool regs = blur_register_ring(w, DP, sizeof(S) == 2 ? kStorageBF16 : kStorageF32);
+    const S* src = static_cast<const S*>(in);
+    S* dst = static_cast<S*>(out);
+    if (sizeof(S) == 2 || groups <= kStagedWavesAtLargeRing) {
+      if (regs && kR128 > 0)
+        k_blur_staged<S, DP, kBlurWavesPerBlock, 128, kR128><<<blocks, kThreads, 0, stream>>>(
+            src, dst, w, st, radius, vertical, ta.table);
+      else
+        k_blur_staged<S, DP, kBlurWavesPerBlock, 128, 0><<<blocks, kThreads, 0, stream>>>(src, dst, w, st, radius,
+                                                                                         vertical, ta.table);
+    } else {
+      if (regs && kR64 > 0)
+        k_blur_staged<S, DP, kBlurWavesPerBlock, 64, kR64><<<blocks, kThreads, 0, stream>>>(src, dst, w, st, radius,
+                                                                                           vertical, ta.table);
+      else
+        k_blur_staged<S, DP, kBlurWavesPerBlock, 64, 0><<<blocks, kThreads, 0, stream>>>(src, dst, w, st, radius,
+                                                                                        vertical, ta.table);
+    }
   } else {
     const int blocks = with_table((blur_reg_waves<DP>(w) + kWavesPerBlock - 1) / kWavesPerBlock, kBlock);
     k_blur<DP, S><<<blocks, kBlock, 0, stream>>>(static_cast<const S*>(in), static_cast<S*>(out), w, st, radius,
@@ -2052,6 +2080,16 @@ hipError_t launch_vad(const void* features, int input_bf16, const int32_t* perm,
 
 bool staged_blur(int dp, int storage) { return dp * (storage == kStorageBF16 ? 2 : 4) >= 16; }
 
+// The second read of a pass's leaving values comes from the 256 MB Infinity
+// Cache when the grid is well inside it, and there the register slots only
+// add work: measured on float32 sorts, 4-64 MiB grids ran 2-4 % faster
+// without them, 256 MiB and larger grids 7-8 % faster with them.
+constexpr int64_t kRegisterRingMinBytes = int64_t(128) << 20;
+
+bool blur_register_ring(int64_t w, int dp, int storage) {
+  return storage == kStorageF32 && staged_blur(dp, storage) && w * w * dp * 4 > kRegisterRingMinBytes;
+}
+
 int batch_blur_blocks(int w, int dp, int storage, int waves_per_block, int64_t max_cells) {
   int64_t blocks = 0, threads = 0;
   int64_t groups = 0, waves = 0;
@@ -2084,23 +2122,35 @@ int assign_blocks_cap(int storage) {
   return PLAS_ASSIGN_MAX_BLOCKS;
 }
 
+template <typename S, int DP, int KR>
+hipError_t blur_batch_staged(const BatchGrid* grids, const uint32_t* map, int blocks, int waves_per_block,
+                             int route, hipStream_t stream) {
+  switch (waves_per_block) {
+    case 1:
+      k_blur_staged_batch<S, DP, 1, KR><<<blocks, 64, 0, stream>>>(grids, map, route);
+      break;
+    case 2:
+      k_blur_staged_batch<S, DP, 2, KR><<<blocks, 128, 0, stream>>>(grids, map, route);
+      break;
+    case 4:
+      k_blur_staged_batch<S, DP, 4, KR><<<blocks, 256, 0, stream>>>(grids, map, route);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipSuccess;
+}
+
 template <typename S, int DP>
 hipError_t blur_batch_dp(const BatchGrid* grids, const uint32_t* map, int blocks, int waves_per_block,
-                         int route, hipStream_t stream) {
+                         int route, int register_ring, hipStream_t stream) {
   if constexpr (staged_cells<S, DP>()) {
-    switch (waves_per_block) {
-      case 1:
-        k_blur_staged_batch<S, DP, 1><<<blocks, 64, 0, stream>>>(grids, map, route);
-        break;
-      case 2:
-        k_blur_staged_batch<S, DP, 2><<<blocks, 128, 0, stream>>>(grids, map, route);
-        break;
-      case 4:
-        k_blur_staged_batch<S, DP, 4><<<blocks, 256, 0, stream>>>(grids, map, route);
-        break;
-      default:
-        return hipErrorInvalidValue;
-    }
+    const hipError_t e =
+        register_ring != 0 && ring_register_chunks<S, kBatchRingRows>() > 0
+            ? blur_batch_staged<S, DP, ring_register_chunks<S, kBatchRingRows>()>(grids, map, blocks,
+                                                                                  waves_per_block, route, stream)
+            : blur_batch_staged<S, DP, 0>(grids, map, blocks, waves_per_block, route, stream);
+    if (e != hipSuccess) return e;
   } else {
     k_blur_batch<DP, S><<<blocks, kBlock, 0, stream>>>(grids, map, route);
   }
@@ -2112,11 +2162,12 @@ int blur_route(int vertical, int src, int dst, int with_table) {
 }
 
 hipError_t launch_blur_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
-                             int waves_per_block, int route, hipStream_t stream) {
+                             int waves_per_block, int route, int register_ring, hipStream_t stream) {
   const int src = (route >> 1) & 3, dst = (route >> 3) & 3;
   if (src > 2 || dst < 1 || dst > 2 || src == dst) return hipErrorInvalidValue;
   PLAS_DISPATCH_STORAGE(storage, {
-    PLAS_DISPATCH_DP(dp, return (blur_batch_dp<SV, DPV>(grids, map, blocks, waves_per_block, route, stream)));
+    PLAS_DISPATCH_DP(dp, return (blur_batch_dp<SV, DPV>(grids, map, blocks, waves_per_block, route, register_ring,
+                                                        stream)));
   });
   return hipSuccess;
 }

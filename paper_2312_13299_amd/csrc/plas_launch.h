@@ -87,6 +87,10 @@ hipError_t launch_vad(const void* features, int input_bf16, const int32_t* perm,
 // Whether blur passes of this shape use the staged kernel (cells of at
 // least 16 bytes); waves_per_block applies to those only.
 bool staged_blur(int dp, int storage);
+// Whether staged float32 passes over a w x w grid of dp channels keep the
+// leaving values in registers (grids of more than 128 MiB) rather than
+// reading them a second time.
+bool blur_register_ring(int64_t w, int dp, int storage);
 // Blur blocks: enough for every line, and for filling a grouping table of
 // max_cells entries at about one entry per thread.
 int batch_blur_blocks(int w, int dp, int storage, int waves_per_block, int64_t max_cells);  // wpb: 1, 2, 4
@@ -98,9 +102,9 @@ int assign_blocks_cap(int storage);  // blocks of an assignment launch without a
 // lines (the first row pass of a reorder).
 int blur_route(int vertical, int src, int dst, int with_table);
 // One blur pass along `route` of every mapped grid, all of dp channels and
-// `storage`.
+// `storage`; register_ring: blur_register_ring holds for these grids.
 hipError_t launch_blur_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
-                             int waves_per_block, int route, hipStream_t stream);
+                             int waves_per_block, int route, int register_ring, hipStream_t stream);
 // One assignment of every mapped grid; each grid's last block runs its
 // control step.
 hipError_t launch_assign_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,

@@ -40,9 +40,17 @@ BLUR_CASES = [
     # (side, d, r)
     (2, 1, 1), (3, 3, 1), (5, 2, 0), (7, 3, 2), (16, 4, 3), (17, 14, 5), (33, 59, 7), (33, 59, 40),
     (64, 59, 31), (64, 64, 1), (100, 3, 9), (129, 16, 63), (256, 59, 127), (250, 8, 300),
-    # float32 radii whose leaving values a wave keeps in registers (48..192),
-    # both ends, and the first radius past them.
-    (97, 59, 48), (301, 59, 192), (301, 59, 193), (1024, 59, 100), (150, 32, 75), (77, 4, 60),
+    # float32 radii of the second load stream on small grids (48..192 and
+    # past them)
+    (97, 59, 48), (301, 59, 192), (301, 59, 193), (150, 32, 75), (77, 4, 60),
+    # float32 grids of more than 128 MiB keep the leaving values of
+    # 48 <= r <= 192 in registers: both ends, the first radius past them,
+    # and cells of 64, 32 and 4 channels
+    (800, 59, 48), (800, 59, 192), (800, 59, 193), (1024, 59, 100), (1100, 32, 75), (3000, 4, 60),
+    # more than 1024 lines of 64 float32 channels: the 64-row ring (leaving
+    # values from the ring up to r = 15, from registers up to r = 64, then
+    # from a second load stream)
+    (1100, 59, 15), (1100, 59, 16), (1100, 59, 64), (1100, 59, 65),
 ]
 
 
