@@ -98,7 +98,6 @@ struct Sort {
 // Lines per block of a sort's blur launches (0 for the register kernel,
 // which has one fixed shape).
 int blur_wpb(const Sort& s) { return plas::staged_blur(s.dp, s.storage) ? s.wpb : 0; }
-int blur_regs(const Sort& s) { return plas::blur_register_ring(s.w, s.dp, s.storage) ? 1 : 0; }
 
 }  // namespace
 
@@ -486,7 +485,14 @@ class BatchRun {
       maps.push_back(std::move(map));
     };
     // Blur launches per (dp, storage, lines per block, register slots);
-    // assignment per (dp, storage).
+    // assignment per (dp, storage). Register slots follow the bytes of all
+    // running grids, which the passes of a reorder stream through together.
+    int64_t working_bytes = 0;
+    for (int slot : run_list_) {
+      const Sort& s = sorts_[slot];
+      working_bytes += s.n * s.dp * (s.storage == plas::kStorageBF16 ? 2 : 4);
+    }
+    auto blur_regs = [&](const Sort& s) { return plas::blur_register_ring(working_bytes, s.dp, s.storage) ? 1 : 0; };
     for (int pass = 0; pass < 2; ++pass) {
       std::vector<std::array<int, 4>> keys;
       auto key_of = [&](const Sort& s) -> std::array<int, 4> {

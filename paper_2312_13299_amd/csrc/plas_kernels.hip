@@ -1979,7 +1979,8 @@ hipError_t blur_pass_dp(const void* in, void* out, int w, const DevState* st, in
     // register slots for the leaving values on grids the Infinity Cache
     // does not hold twice over.
     constexpr int kR128 = ring_register_chunks<S, 128>(), kR64 = ring_register_chunks<S, 64>();
-    const bool regs = blur_register_ring(w, DP, sizeof(S) == 2 ? kStorageBF16 : kStorageF32);
+    const bool regs = blur_register_ring(static_cast<int64_t>(w) * w * DP * static_cast<int64_t>(sizeof(S)), DP,
+                                         sizeof(S) == 2 ? kStorageBF16 : kStorageF32);
     const S* src = static_cast<const S*>(in);
     S* dst = static_cast<S*>(out);
     if (sizeof(S) == 2 || groups <= kStagedWavesAtLargeRing) {
@@ -2081,13 +2082,14 @@ hipError_t launch_vad(const void* features, int input_bf16, const int32_t* perm,
 bool staged_blur(int dp, int storage) { return dp * (storage == kStorageBF16 ? 2 : 4) >= 16; }
 
 // The second read of a pass's leaving values comes from the 256 MB Infinity
-// Cache when the grid is well inside it, and there the register slots only
-// add work: measured on float32 sorts, 4-64 MiB grids ran 2-4 % faster
-// without them, 256 MiB and larger grids 7-8 % faster with them.
+// Cache when the grids in flight are well inside it, and there the register
+// slots only add work: measured on float32 sorts, single 4-64 MiB grids ran
+// 2-4 % faster without them; single 256 MiB and larger grids, and a batch
+// of 64 grids of up to 121 MiB (3 GB together), ran 3-8 % faster with them.
 constexpr int64_t kRegisterRingMinBytes = int64_t(128) << 20;
 
-bool blur_register_ring(int64_t w, int dp, int storage) {
-  return storage == kStorageF32 && staged_blur(dp, storage) && w * w * dp * 4 > kRegisterRingMinBytes;
+bool blur_register_ring(int64_t working_bytes, int dp, int storage) {
+  return storage == kStorageF32 && staged_blur(dp, storage) && working_bytes > kRegisterRingMinBytes;
 }
 
 int batch_blur_blocks(int w, int dp, int storage, int waves_per_block, int64_t max_cells) {

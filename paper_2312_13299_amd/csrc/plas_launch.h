@@ -87,10 +87,11 @@ hipError_t launch_vad(const void* features, int input_bf16, const int32_t* perm,
 // Whether blur passes of this shape use the staged kernel (cells of at
 // least 16 bytes); waves_per_block applies to those only.
 bool staged_blur(int dp, int storage);
-// Whether staged float32 passes over a w x w grid of dp channels keep the
-// leaving values in registers (grids of more than 128 MiB) rather than
-// reading them a second time.
-bool blur_register_ring(int64_t w, int dp, int storage);
+// Whether staged float32 passes of dp channels keep the leaving values in
+// registers rather than reading them a second time: when the grids in
+// flight (the one grid of a sort, every running grid of a batch) hold more
+// than 128 MiB.
+bool blur_register_ring(int64_t working_bytes, int dp, int storage);
 // Blur blocks: enough for every line, and for filling a grouping table of
 // max_cells entries at about one entry per thread.
 int batch_blur_blocks(int w, int dp, int storage, int waves_per_block, int64_t max_cells);  // wpb: 1, 2, 4
