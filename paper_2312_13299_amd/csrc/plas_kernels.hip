@@ -622,14 +622,14 @@ __device__ __forceinline__ void dma16(const void* src, uint32_t m0) {
 }
 #pragma clang diagnostic pop
 
-// Cache hints of the two load streams: the leaving stream (a second read of
+// Cache hints of the two load streams. The leaving stream (a second read of
 // positions the entering stream read 2r + 1 positions earlier) streams
 // through, so that it does not evict entering data the L2 still holds for
-// it; see kBlurEnterStream for the entering stream.
-#ifndef PLAS_BLUR_ENTER_NT
-#define PLAS_BLUR_ENTER_NT 0
-#endif
-constexpr bool kBlurEnterStream = PLAS_BLUR_ENTER_NT;
+// it. The entering stream streams in the column pass only: its input H is
+// dead after that pass, and keeping H out of the Infinity Cache leaves room
+// for G and T, which the assignment reads next (1024^2 float32: column pass
+// 98 -> 87 us, assignment 110 -> 104 us at r <= 15). Streaming the row pass's
+// loads of G as well made the column pass slower again (101 us).
 constexpr bool kBlurLeaveStream = true;
 
 // s_waitcnt vmcnt(n) for a run-time n (rounded down, which only waits
@@ -677,6 +677,7 @@ struct RingLine {
   int lag;       // the leaving chunk needed at step e is e - lag (split ring)
   int n_steps;   // A + M
   int q, j, lane;
+  bool vertical;     // column pass (its entering loads stream)
   bool split;        // the leaving values have their own region (the ring's upper half)
   bool regs;         // split, and the leaving chunks come from registers instead of a second load stream
   int enter_mask;    // ring rows of the entering stream - 1
@@ -708,7 +709,12 @@ struct RingLine {
     return split && !regs && u - lag >= 0 && u - lag < n_chunks;
   }
   __device__ __forceinline__ void issue(int u) const {
-    if (slot_enter(u)) load_chunk<kBlurEnterStream>(u, (u * kChunk) & enter_mask);
+    if (slot_enter(u)) {
+      if (vertical)
+        load_chunk<true>(u, (u * kChunk) & enter_mask);
+      else
+        load_chunk<false>(u, (u * kChunk) & enter_mask);
+    }
     if (slot_leave(u))
       load_chunk<kBlurLeaveStream>(u - lag, Sh::kHalfRows + (((u - lag) * kChunk) & (Sh::kHalfRows - 1)));
   }
@@ -970,6 +976,7 @@ __device__ __forceinline__ void blur_staged_line(const S* __restrict__ in, S* __
   L.ld_ok = ld_line < w;
   L.ld_off = line_off(L.ld_ok ? ld_line : w - 1) + (L.j % L_t::kPiecesPerCell) * (16 / static_cast<int>(sizeof(S)));
   L.lane = lane;
+  L.vertical = vertical != 0;
   L.lds = lds;
   if (r == 0) {
     const int64_t own_line = line0 + lane / DP;
