@@ -69,7 +69,7 @@ struct Launch {
   int dp;
   int storage;
   int wpb;
-  int regs;        // blur: leaving values in registers (plas::blur_register_ring)
+  int large;       // blur: the running grids are a large working set (plas::blur_large_working_set)
   size_t map_off;  // byte offset of the block map in the plan
   int blocks;
 };
@@ -484,19 +484,19 @@ class BatchRun {
       launches_.push_back(L);
       maps.push_back(std::move(map));
     };
-    // Blur launches per (dp, storage, lines per block, register slots);
-    // assignment per (dp, storage). Register slots follow the bytes of all
-    // running grids, which the passes of a reorder stream through together.
+    // Blur launches per (dp, storage, lines per block); assignment per (dp,
+    // storage). The working set is the bytes of all running grids, which the
+    // passes of a reorder stream through together.
     int64_t working_bytes = 0;
     for (int slot : run_list_) {
       const Sort& s = sorts_[slot];
       working_bytes += s.n * s.dp * (s.storage == plas::kStorageBF16 ? 2 : 4);
     }
-    auto blur_regs = [&](const Sort& s) { return plas::blur_register_ring(working_bytes, s.dp, s.storage) ? 1 : 0; };
+    const int large = plas::blur_large_working_set(working_bytes) ? 1 : 0;
     for (int pass = 0; pass < 2; ++pass) {
       std::vector<std::array<int, 4>> keys;
       auto key_of = [&](const Sort& s) -> std::array<int, 4> {
-        return {s.dp, s.storage, pass == 0 ? blur_wpb(s) : 0, pass == 0 ? blur_regs(s) : 0};
+        return {s.dp, s.storage, pass == 0 ? blur_wpb(s) : 0, pass == 0 ? large : 0};
       };
       for (int slot : run_list_) {
         const std::array<int, 4> k = key_of(sorts_[slot]);
@@ -553,7 +553,7 @@ class BatchRun {
         for (const Launch& L : launches_)
           if (L.kind == kBlur)
             PLAS_HIP(h_, plas::launch_blur_batch(grids, map_of(L), L.blocks, L.dp, L.storage, L.wpb == 0 ? 4 : L.wpb,
-                                                 route, L.regs, stream));
+                                                 route, L.large, stream));
       if (timed) PLAS_HIP(h_, hipEventRecord(b_->events[3 * i + 1], stream));
       for (const Launch& L : launches_)
         if (L.kind == kAssign)

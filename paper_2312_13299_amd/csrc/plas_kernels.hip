@@ -625,11 +625,13 @@ __device__ __forceinline__ void dma16(const void* src, uint32_t m0) {
 // Cache hints of the two load streams. The leaving stream (a second read of
 // positions the entering stream read 2r + 1 positions earlier) streams
 // through, so that it does not evict entering data the L2 still holds for
-// it. The entering stream streams in the column pass only: its input H is
-// dead after that pass, and keeping H out of the Infinity Cache leaves room
-// for G and T, which the assignment reads next (1024^2 float32: column pass
-// 98 -> 87 us, assignment 110 -> 104 us at r <= 15). Streaming the row pass's
-// loads of G as well made the column pass slower again (101 us).
+// it. The entering stream streams in the column pass when the grids in
+// flight exceed 128 MiB (blur_large_working_set): its input H is dead after
+// that pass, and keeping H out of the Infinity Cache leaves room for G and
+// T, which the assignment reads next (1024^2 float32: column pass 98 -> 87
+// us, assignment 110 -> 104 us at r <= 15). Streaming the row pass's loads
+// of G as well made the column pass slower again (101 us); grids the cache
+// holds whole ran 1-2 % slower with streaming column loads.
 constexpr bool kBlurLeaveStream = true;
 
 // s_waitcnt vmcnt(n) for a run-time n (rounded down, which only waits
@@ -660,7 +662,7 @@ __device__ __forceinline__ void wait_vm_dyn(int n) {
   }
 }
 
-template <typename S, int DP, int RR, int KR>
+template <typename S, int DP, int RR, int KR, bool NT>
 struct RingLine {
   using Sh = RingShape<S, RR, KR>;
   static constexpr int kChunk = Sh::kChunk;
@@ -677,7 +679,6 @@ struct RingLine {
   int lag;       // the leaving chunk needed at step e is e - lag (split ring)
   int n_steps;   // A + M
   int q, j, lane;
-  bool vertical;     // column pass (its entering loads stream)
   bool split;        // the leaving values have their own region (the ring's upper half)
   bool regs;         // split, and the leaving chunks come from registers instead of a second load stream
   int enter_mask;    // ring rows of the entering stream - 1
@@ -709,12 +710,7 @@ struct RingLine {
     return split && !regs && u - lag >= 0 && u - lag < n_chunks;
   }
   __device__ __forceinline__ void issue(int u) const {
-    if (slot_enter(u)) {
-      if (vertical)
-        load_chunk<true>(u, (u * kChunk) & enter_mask);
-      else
-        load_chunk<false>(u, (u * kChunk) & enter_mask);
-    }
+    if (slot_enter(u)) load_chunk<NT>(u, (u * kChunk) & enter_mask);
     if (slot_leave(u))
       load_chunk<kBlurLeaveStream>(u - lag, Sh::kHalfRows + (((u - lag) * kChunk) & (Sh::kHalfRows - 1)));
   }
@@ -957,11 +953,11 @@ struct RingLine {
 
 // Lines line0 .. line0 + 64/DP - 1 of a staged blur pass (those below w),
 // by one wave.
-template <typename S, int DP, int RR, int KR>
+template <typename S, int DP, int RR, int KR, bool NT>
 __device__ __forceinline__ void blur_staged_line(const S* __restrict__ in, S* __restrict__ out, int w, int r,
                                                  int vertical, int64_t line0, int lane, RingLds<S, RR>* lds) {
   using Sh = RingShape<S, RR, KR>;
-  using L_t = RingLine<S, DP, RR, KR>;
+  using L_t = RingLine<S, DP, RR, KR, NT>;
   L_t L;
   // Element offset of line l at position 0, and between positions.
   auto line_off = [&](int64_t l) { return vertical ? l * DP : l * w * DP; };
@@ -976,7 +972,6 @@ __device__ __forceinline__ void blur_staged_line(const S* __restrict__ in, S* __
   L.ld_ok = ld_line < w;
   L.ld_off = line_off(L.ld_ok ? ld_line : w - 1) + (L.j % L_t::kPiecesPerCell) * (16 / static_cast<int>(sizeof(S)));
   L.lane = lane;
-  L.vertical = vertical != 0;
   L.lds = lds;
   if (r == 0) {
     const int64_t own_line = line0 + lane / DP;
@@ -1011,26 +1006,27 @@ constexpr int staged_waves_per_eu() {
 // One group of 64/DP lines per wave, WPB waves per block: block `bid` of
 // `nblocks` takes groups bid * WPB + wave, and walks on with a stride if
 // there are more groups than waves.
-template <typename S, int DP, int WPB, int RR, int KR>
+template <typename S, int DP, int WPB, int RR, int KR, bool NT>
 __device__ __forceinline__ void blur_staged_lines(const S* __restrict__ in, S* __restrict__ out, int w, int r,
                                                   int vertical, int64_t bid, int64_t nblocks, RingLds<S, RR>* stage) {
   constexpr int kLinesPerWave = 64 / DP;
   const int wib = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   for (int64_t g = bid * WPB + wib; g * kLinesPerWave < w; g += nblocks * WPB)
-    blur_staged_line<S, DP, RR, KR>(in, out, w, r, vertical, g * kLinesPerWave, lane, stage + wib);
+    blur_staged_line<S, DP, RR, KR, NT>(in, out, w, r, vertical, g * kLinesPerWave, lane, stage + wib);
 }
 
 // Staged blur pass for cells of at least 16 bytes (DP * sizeof(S) >= 16),
-// with a ring of RR rows per wave and KR register slots.
-template <typename S, int DP, int WPB, int RR, int KR>
+// with a ring of RR rows per wave and KR register slots; NT: the entering
+// loads stream.
+template <typename S, int DP, int WPB, int RR, int KR, bool NT>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(staged_waves_per_eu<S, RR>())))
 void k_blur_staged(const S* __restrict__ in, S* __restrict__ out, int w, const DevState* __restrict__ st, int radius,
                    int vertical, int32_t* __restrict__ table) {
   __shared__ RingLds<S, RR> s_stage[WPB];
   int r;
   if (!pass_radius(st, radius, r)) return;
-  blur_staged_lines<S, DP, WPB, RR, KR>(in, out, w, r, vertical, blockIdx.x, gridDim.x, s_stage);
+  blur_staged_lines<S, DP, WPB, RR, KR, NT>(in, out, w, r, vertical, blockIdx.x, gridDim.x, s_stage);
   if (table != nullptr) fill_group_table<WPB * 64>(table, st->beta, st->keys, blockIdx.x, gridDim.x);
 }
 
@@ -1745,7 +1741,7 @@ __device__ __forceinline__ T* global_ptr(U PLAS_GLOBAL* p) {
 // A batch blur pass's route (see launch_blur_batch): its axis, source and
 // destination grids (0 G, 1 H, 2 T) and whether it fills the grouping table
 // afterwards (the first row pass of a reorder).
-__device__ __forceinline__ int route_vertical(int route) { return route & 1; }
+__host__ __device__ __forceinline__ int route_vertical(int route) { return route & 1; }
 __device__ __forceinline__ bool route_table(int route) { return (route >> 5) & 1; }
 template <typename S>
 __device__ __forceinline__ S* route_grid(const BatchGridView& g, int sel) {
@@ -1756,7 +1752,7 @@ __device__ __forceinline__ S* route_grid(const BatchGridView& g, int sel) {
 // by the thousand; the larger ring keeps leaving values on chip up to r = 47).
 constexpr int kBatchRingRows = 128;
 
-template <typename S, int DP, int WPB, int KR>
+template <typename S, int DP, int WPB, int KR, bool NT>
 __global__ __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(staged_waves_per_eu<S, kBatchRingRows>())))
 void k_blur_staged_batch(const BatchGrid* __restrict__ grids, const uint32_t* __restrict__ map, int route) {
   __shared__ RingLds<S, kBatchRingRows> s_stage[WPB];
@@ -1768,7 +1764,7 @@ void k_blur_staged_batch(const BatchGrid* __restrict__ grids, const uint32_t* __
   const int vertical = route_vertical(route);
   const S* in = route_grid<S>(g, (route >> 1) & 3);
   S* out = route_grid<S>(g, (route >> 3) & 3);
-  blur_staged_lines<S, DP, WPB, kBatchRingRows, KR>(in, out, g.w, r, vertical, local, g.blur_blocks, s_stage);
+  blur_staged_lines<S, DP, WPB, kBatchRingRows, KR, NT>(in, out, g.w, r, vertical, local, g.blur_blocks, s_stage);
   if (route_table(route))
     fill_group_table<WPB * 64>(global_ptr<int32_t>(g.table), st->beta, st->keys, local, g.blur_blocks);
 }
@@ -1965,6 +1961,24 @@ hipError_t launch_gather(const void* X, const int32_t* P, void* G, int64_t n, in
   return hipGetLastError();
 }
 
+// A staged pass with ring RR: over a large working set with register slots
+// (float32) and, in the column pass, streaming entering loads; else with
+// neither.
+template <typename S, int DP, int WPB, int RR>
+hipError_t staged_launch(int blocks, bool large, int vertical, hipStream_t stream, const S* src, S* dst, int w,
+                         const DevState* st, int radius, int32_t* table) {
+  constexpr int kR = ring_register_chunks<S, RR>();
+  constexpr int kThreads = WPB * 64;
+  if (!large)
+    k_blur_staged<S, DP, WPB, RR, 0, false><<<blocks, kThreads, 0, stream>>>(src, dst, w, st, radius, vertical, table);
+  else if (vertical)
+    k_blur_staged<S, DP, WPB, RR, kR, true><<<blocks, kThreads, 0, stream>>>(src, dst, w, st, radius, vertical, table);
+  else
+    k_blur_staged<S, DP, WPB, RR, kR, false><<<blocks, kThreads, 0, stream>>>(src, dst, w, st, radius, vertical,
+                                                                             table);
+  return hipGetLastError();
+}
+
 // One pass for storage S and DP channels: the staged kernel when cells
 // hold whole 16-byte pieces, else the register kernel.
 template <typename S, int DP>
@@ -1983,28 +1997,16 @@ hipError_t blur_pass_dp(const void* in, void* out, int w, const DevState* st, in
     const int blocks = with_table((groups + kBlurWavesPerBlock - 1) / kBlurWavesPerBlock, kThreads);
     // The 128-row ring while every wave of the pass fits on the chip at
     // once with it (4 float32 waves per CU), else the 64-row ring (8 per CU);
-    // register slots for the leaving values on grids the Infinity Cache
-    // does not hold twice over.
-    constexpr int kR128 = ring_register_chunks<S, 128>(), kR64 = ring_register_chunks<S, 64>();
-    const bool regs = blur_register_ring(static_cast<int64_t>(w) * w * DP * static_cast<int64_t>(sizeof(S)), DP,
-                                         sizeof(S) == 2 ? kStorageBF16 : kStorageF32);
+    // register slots for the leaving values and streaming column loads on
+    // grids the Infinity Cache does not hold twice over.
+    const bool large = blur_large_working_set(static_cast<int64_t>(w) * w * DP * static_cast<int64_t>(sizeof(S)));
     const S* src = static_cast<const S*>(in);
     S* dst = static_cast<S*>(out);
-    if (sizeof(S) == 2 || groups <= kStagedWavesAtLargeRing) {
-      if (regs && kR128 > 0)
-        k_blur_staged<S, DP, kBlurWavesPerBlock, 128, kR128><<<blocks, kThreads, 0, stream>>>(
-            src, dst, w, st, radius, vertical, ta.table);
-      else
-        k_blur_staged<S, DP, kBlurWavesPerBlock, 128, 0><<<blocks, kThreads, 0, stream>>>(src, dst, w, st, radius,
-                                                                                         vertical, ta.table);
-    } else {
-      if (regs && kR64 > 0)
-        k_blur_staged<S, DP, kBlurWavesPerBlock, 64, kR64><<<blocks, kThreads, 0, stream>>>(src, dst, w, st, radius,
-                                                                                           vertical, ta.table);
-      else
-        k_blur_staged<S, DP, kBlurWavesPerBlock, 64, 0><<<blocks, kThreads, 0, stream>>>(src, dst, w, st, radius,
-                                                                                        vertical, ta.table);
-    }
+    if (sizeof(S) == 2 || groups <= kStagedWavesAtLargeRing)
+      return staged_launch<S, DP, kBlurWavesPerBlock, 128>(blocks, large, vertical, stream, src, dst, w, st, radius,
+                                                           ta.table);
+    return staged_launch<S, DP, kBlurWavesPerBlock, 64>(blocks, large, vertical, stream, src, dst, w, st, radius,
+                                                        ta.table);
   } else {
     const int blocks = with_table((blur_reg_waves<DP>(w) + kWavesPerBlock - 1) / kWavesPerBlock, kBlock);
     k_blur<DP, S><<<blocks, kBlock, 0, stream>>>(static_cast<const S*>(in), static_cast<S*>(out), w, st, radius,
@@ -2093,11 +2095,10 @@ bool staged_blur(int dp, int storage) { return dp * (storage == kStorageBF16 ? 2
 // slots only add work: measured on float32 sorts, single 4-64 MiB grids ran
 // 2-4 % faster without them; single 256 MiB and larger grids, and a batch
 // of 64 grids of up to 121 MiB (3 GB together), ran 3-8 % faster with them.
-constexpr int64_t kRegisterRingMinBytes = int64_t(128) << 20;
+// The same bound decides the column pass's streaming loads.
+constexpr int64_t kLargeWorkingSetBytes = int64_t(128) << 20;
 
-bool blur_register_ring(int64_t working_bytes, int dp, int storage) {
-  return storage == kStorageF32 && staged_blur(dp, storage) && working_bytes > kRegisterRingMinBytes;
-}
+bool blur_large_working_set(int64_t working_bytes) { return working_bytes > kLargeWorkingSetBytes; }
 
 int batch_blur_blocks(int w, int dp, int storage, int waves_per_block, int64_t max_cells) {
   int64_t blocks = 0, threads = 0;
@@ -2131,18 +2132,18 @@ int assign_blocks_cap(int storage) {
   return PLAS_ASSIGN_MAX_BLOCKS;
 }
 
-template <typename S, int DP, int KR>
+template <typename S, int DP, int KR, bool NT>
 hipError_t blur_batch_staged(const BatchGrid* grids, const uint32_t* map, int blocks, int waves_per_block,
                              int route, hipStream_t stream) {
   switch (waves_per_block) {
     case 1:
-      k_blur_staged_batch<S, DP, 1, KR><<<blocks, 64, 0, stream>>>(grids, map, route);
+      k_blur_staged_batch<S, DP, 1, KR, NT><<<blocks, 64, 0, stream>>>(grids, map, route);
       break;
     case 2:
-      k_blur_staged_batch<S, DP, 2, KR><<<blocks, 128, 0, stream>>>(grids, map, route);
+      k_blur_staged_batch<S, DP, 2, KR, NT><<<blocks, 128, 0, stream>>>(grids, map, route);
       break;
     case 4:
-      k_blur_staged_batch<S, DP, 4, KR><<<blocks, 256, 0, stream>>>(grids, map, route);
+      k_blur_staged_batch<S, DP, 4, KR, NT><<<blocks, 256, 0, stream>>>(grids, map, route);
       break;
     default:
       return hipErrorInvalidValue;
@@ -2152,13 +2153,13 @@ hipError_t blur_batch_staged(const BatchGrid* grids, const uint32_t* map, int bl
 
 template <typename S, int DP>
 hipError_t blur_batch_dp(const BatchGrid* grids, const uint32_t* map, int blocks, int waves_per_block,
-                         int route, int register_ring, hipStream_t stream) {
+                         int route, int large, hipStream_t stream) {
   if constexpr (staged_cells<S, DP>()) {
+    constexpr int kR = ring_register_chunks<S, kBatchRingRows>();
     const hipError_t e =
-        register_ring != 0 && ring_register_chunks<S, kBatchRingRows>() > 0
-            ? blur_batch_staged<S, DP, ring_register_chunks<S, kBatchRingRows>()>(grids, map, blocks,
-                                                                                  waves_per_block, route, stream)
-            : blur_batch_staged<S, DP, 0>(grids, map, blocks, waves_per_block, route, stream);
+        large == 0 ? blur_batch_staged<S, DP, 0, false>(grids, map, blocks, waves_per_block, route, stream)
+        : route_vertical(route) ? blur_batch_staged<S, DP, kR, true>(grids, map, blocks, waves_per_block, route, stream)
+                                : blur_batch_staged<S, DP, kR, false>(grids, map, blocks, waves_per_block, route, stream);
     if (e != hipSuccess) return e;
   } else {
     k_blur_batch<DP, S><<<blocks, kBlock, 0, stream>>>(grids, map, route);
@@ -2171,12 +2172,11 @@ int blur_route(int vertical, int src, int dst, int with_table) {
 }
 
 hipError_t launch_blur_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
-                             int waves_per_block, int route, int register_ring, hipStream_t stream) {
+                             int waves_per_block, int route, int large, hipStream_t stream) {
   const int src = (route >> 1) & 3, dst = (route >> 3) & 3;
   if (src > 2 || dst < 1 || dst > 2 || src == dst) return hipErrorInvalidValue;
   PLAS_DISPATCH_STORAGE(storage, {
-    PLAS_DISPATCH_DP(dp, return (blur_batch_dp<SV, DPV>(grids, map, blocks, waves_per_block, route, register_ring,
-                                                        stream)));
+    PLAS_DISPATCH_DP(dp, return (blur_batch_dp<SV, DPV>(grids, map, blocks, waves_per_block, route, large, stream)));
   });
   return hipSuccess;
 }

@@ -87,11 +87,11 @@ hipError_t launch_vad(const void* features, int input_bf16, const int32_t* perm,
 // Whether blur passes of this shape use the staged kernel (cells of at
 // least 16 bytes); waves_per_block applies to those only.
 bool staged_blur(int dp, int storage);
-// Whether staged float32 passes of dp channels keep the leaving values in
-// registers rather than reading them a second time: when the grids in
-// flight (the one grid of a sort, every running grid of a batch) hold more
-// than 128 MiB.
-bool blur_register_ring(int64_t working_bytes, int dp, int storage);
+// Whether the grids in flight (the one grid of a sort, every running grid
+// of a batch) are a large working set, more than 128 MiB: then staged
+// float32 passes keep the leaving values in registers rather than reading
+// them a second time, and column passes stream their loads.
+bool blur_large_working_set(int64_t working_bytes);
 // Blur blocks: enough for every line, and for filling a grouping table of
 // max_cells entries at about one entry per thread.
 int batch_blur_blocks(int w, int dp, int storage, int waves_per_block, int64_t max_cells);  // wpb: 1, 2, 4
@@ -103,9 +103,9 @@ int assign_blocks_cap(int storage);  // blocks of an assignment launch without a
 // lines (the first row pass of a reorder).
 int blur_route(int vertical, int src, int dst, int with_table);
 // One blur pass along `route` of every mapped grid, all of dp channels and
-// `storage`; register_ring: blur_register_ring holds for these grids.
+// `storage`; large: blur_large_working_set holds for the running grids.
 hipError_t launch_blur_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
-                             int waves_per_block, int route, int register_ring, hipStream_t stream);
+                             int waves_per_block, int route, int large, hipStream_t stream);
 // One assignment of every mapped grid; each grid's last block runs its
 // control step.
 hipError_t launch_assign_batch(const BatchGrid* grids, const uint32_t* map, int blocks, int dp, int storage,
