@@ -925,10 +925,11 @@ struct RingLine {
       int slot = 0;
       for (int e = 0; e < n_steps; ++e) {
         if (slot_loads(e) > 0) wait_vm_dyn(ops_after(e));
+        if (Sh::kEarly) issue(e + Sh::kDepth - 1);
         exchange<Sh::kRegChunks>(keep, slot, e);
         if (e * kChunk <= first_hi) start_sum(e, s);
         if (e >= ahead) outputs(e - ahead, s);
-        issue(e + Sh::kDepth - 1);
+        if (!Sh::kEarly) issue(e + Sh::kDepth - 1);
         slot = slot + 1 == lag ? 0 : slot + 1;
       }
     }
