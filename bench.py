@@ -79,6 +79,63 @@ def measured_traffic(kernel: str, workload: str):
     return None if k is None else int(k["hbm_bytes_per_launch"])
 
 
+def pmc_command(counter: str, out_dir: str, workload: str) -> str:
+    """The rocprofv3 run whose per-dispatch `counter` values a traffic record
+    is built from (one counter per run, the copy probe included)."""
+    return (f"rocprofv3 --pmc {counter} -T --kernel-include-regex 'k_blur|k_assign|elementwise' -d {out_dir} "
+            f"-o run -f csv -- python3 bench.py --workload {workload} --steps 1 --warmup 0 --no-cpu-baseline "
+            f"--no-fp32-compare --no-precision --copy-probe")
+
+
+def traffic_record(workload: str, fetch_dir: str, write_dir: str) -> dict:
+    """HBM bytes per launch of the blur pass and the assignment from two
+    rocprofv3 --pmc runs of this script (pmc_command): FETCH_SIZE and
+    WRITE_SIZE in KiB per dispatch, each divided by what the same counter
+    reads for the copy probe (2^26 floats read and written by one
+    elementwise kernel). Blur launches queued after the end of a sort
+    return at once and are left out."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        vals = {}
+        for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] != counter:
+                        continue
+                    k = r["Kernel_Name"]
+                    key = ("blur_pass" if "k_blur" in k else "assign" if "k_assign" in k
+                           else "copy" if "elementwise" in k else None)
+                    if key is not None:
+                        vals.setdefault(key, []).append(float(r["Counter_Value"]))
+        return vals
+
+    fv, wv = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    copy_bytes = (1 << 26) * 4
+    # The probe's first kernel fills its source (writes only): take the copies.
+    copies = [v for v in fv["copy"] if v > 1024]
+    ff = sum(copies) / len(copies) * 1024 / copy_bytes
+    wf = sum(wv["copy"]) / len(wv["copy"]) * 1024 / copy_bytes
+    rec = {"workload": f"plas_sort ({workload} workload, one full sort)",
+           "kernel_source_sha256": kernel_source_hash(),
+           "copy_probe": {"bytes_read": copy_bytes, "bytes_written": copy_bytes,
+                          "fetch_counter_factor": round(ff, 4), "write_counter_factor": round(wf, 4)},
+           "commands": {"fetch": pmc_command("FETCH_SIZE", fetch_dir, workload),
+                        "write": pmc_command("WRITE_SIZE", write_dir, workload),
+                        "record": f"python3 bench.py --workload {workload} --write-traffic {fetch_dir} {write_dir}"},
+           "kernels": {}}
+    for k in ("blur_pass", "assign"):
+        fs = [v for v in fv[k] if v > 1024]
+        ws = [v for v in wv.get(k, []) if v > 0]
+        n = min(len(fs), len(ws)) if k == "blur_pass" else len(fs)
+        fm = sum(fs) / len(fs)
+        wm = sum(ws) / len(ws) if ws else 0.0
+        rec["kernels"][k] = {"launches": n, "fetch_kib_raw": round(fm, 1), "write_kib_raw": round(wm, 1),
+                             "hbm_bytes_per_launch": int(fm * 1024 / ff + wm * 1024 / wf)}
+    return rec
+
+
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -533,7 +590,20 @@ def main() -> int:
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain elementwise copy of 256 MiB (read and write 2^26 "
                          "floats) to calibrate HBM byte counters")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="scene / precision workload: write profiles/hbm_traffic_<name>.json from the "
+                         "output folders of the two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
     args = ap.parse_args()
+    if args.write_traffic:
+        if args.workload not in ("scene", "precision"):
+            print("--write-traffic applies to the scene and precision workloads", file=sys.stderr)
+            return 2
+        name = "sort_1448_d59_bf16" if args.workload == "precision" else "sort_1024_d59"
+        rec = traffic_record(args.workload, *args.write_traffic)
+        with open(os.path.join(PROFILES, f"hbm_traffic_{name}.json"), "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec, indent=1))
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the PLAS sort of one grid is a single-device "
               f"workload here (asked for --gpus {args.gpus})", file=sys.stderr)

@@ -525,8 +525,8 @@ __device__ __forceinline__ Q load_quad(const Q* p) {
 // rows (1 KB): load lane (q, j) moves the 16-byte piece j of position q, piece
 // j belonging to line j / kPiecesPerCell, and the data goes straight to LDS
 // without passing through registers, so several chunks can be in flight per
-// wave. Outputs are summed into LDS rows and leave as 16-byte stores with a
-// streaming hint.
+// wave. Outputs are summed into LDS rows and leave as 16-byte stores (cache
+// hints: blur_stream_stores).
 //
 // Chunks are kChunk positions aligned to multiples of kChunk (a row walk then
 // reads and writes whole aligned 4 KB blocks). The line is loaded chunk by
@@ -536,10 +536,10 @@ __device__ __forceinline__ Q load_quad(const Q* p) {
 // lies in chunk e or e - 1). While the ring also holds every leaving position
 // x - r - 1 still to come beside the chunks in flight, leaving values are read
 // back from it; otherwise the ring is split in two halves and the leaving
-// chunks reach the upper half from registers (float32, up to 24 chunks back
-// with the 128-row ring: 48 <= r <= 192; 8 with the 64-row ring:
-// 16 <= r <= 64), where each chunk was kept since it entered, or from a
-// second load stream (the same positions again).
+// chunks reach the upper half from KR register slots, where each chunk was
+// kept since it entered (float32 over large working sets: 24 slots with the
+// 128-row ring, 48 <= r <= 192; 8 with the 64-row ring, 16 <= r <= 64), or
+// from a second load stream (the same positions again).
 // Loads are issued at positions clamped into the line (a clamped load fetches
 // a value the sums never use), so every chunk is exactly kVec load
 // instructions.

@@ -104,3 +104,44 @@ def test_energy_f64_matches_the_oracle_definition(ref, side, d, r):
     got = bench.energy_f64(torch, torch.from_numpy(F), torch.from_numpy(perm), side, r)
     want = ref.grid_energy_f64(F, perm, side, r)
     assert got == pytest.approx(want, rel=1e-12, abs=1e-15)
+
+
+def _counter_csv(path, rows):
+    import csv
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, "run_counter_collection.csv"), "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for k, c, v in rows:
+            w.writerow({"Kernel_Name": k, "Counter_Name": c, "Counter_Value": v})
+
+
+def test_traffic_record_scales_by_the_copy_probe(tmp_path):
+    """The traffic record divides each counter by what it reads for the copy
+    probe: a FETCH_SIZE that reports half the copy's 256 MiB and a WRITE_SIZE
+    that reports all of it give factors 0.5 and 1, and a blur pass that
+    fetches 100 MiB and writes 50 MiB by those counters moves 250 MiB."""
+    mib = 1024  # KiB
+    fetch = tmp_path / "f"
+    write = tmp_path / "w"
+    copy = "void at::native::elementwise_kernel<...>"
+    _counter_csv(str(fetch), [
+        (copy, "FETCH_SIZE", 0.5),                      # the probe's fill: ignored
+        (copy, "FETCH_SIZE", 128 * mib), (copy, "FETCH_SIZE", 128 * mib),
+        ("k_blur_staged<...>", "FETCH_SIZE", 100 * mib), ("k_blur_staged<...>", "FETCH_SIZE", 100 * mib),
+        ("k_blur_staged<...>", "FETCH_SIZE", 0.25),     # a pass queued after the end of the sort
+        ("k_assign<...>", "FETCH_SIZE", 200 * mib),
+    ])
+    _counter_csv(str(write), [
+        (copy, "WRITE_SIZE", 256 * mib), (copy, "WRITE_SIZE", 256 * mib), (copy, "WRITE_SIZE", 256 * mib),
+        ("k_blur_staged<...>", "WRITE_SIZE", 50 * mib), ("k_blur_staged<...>", "WRITE_SIZE", 50 * mib),
+        ("k_blur_staged<...>", "WRITE_SIZE", 0.0),
+        ("k_assign<...>", "WRITE_SIZE", 4 * mib),
+    ])
+    rec = bench.traffic_record("scene", str(fetch), str(write))
+    assert rec["copy_probe"]["fetch_counter_factor"] == 0.5 and rec["copy_probe"]["write_counter_factor"] == 1.0
+    blur = rec["kernels"]["blur_pass"]
+    assert blur["launches"] == 2 and blur["hbm_bytes_per_launch"] == 250 << 20
+    assert rec["kernels"]["assign"]["hbm_bytes_per_launch"] == (400 + 4) << 20
+    assert rec["kernel_source_sha256"] == bench.kernel_source_hash()
+    assert "--workload scene" in rec["commands"]["fetch"] and "--pmc FETCH_SIZE" in rec["commands"]["fetch"]
