@@ -919,7 +919,9 @@ struct RingLine {
 
   __device__ __forceinline__ void run_regs() const {
     if constexpr (Sh::kRegChunks > 0) {
-      Word keep[Sh::kRegChunks][kWords];
+      // Zeroed: the first lag steps read a slot (and drop the value) before
+      // its first chunk arrives.
+      Word keep[Sh::kRegChunks][kWords] = {};
       for (int u = 0; u <= Sh::kDepth - 2; ++u) issue(u);
       float s = 0.0f;
       int slot = 0;
