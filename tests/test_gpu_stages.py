@@ -65,6 +65,32 @@ def test_blur_bitwise(env, side, d, r):
     assert np.array_equal(bits(T), bits(want))
 
 
+# Radius sweeps over the boundaries of the ways a pass gets its leaving
+# values, on grids large enough for the register slots (more than 128 MiB):
+# with the 128-row ring the ring itself (r <= 47), registers (48..192) and a
+# second load stream (r > 192, up to r > w / 2); with the 64-row ring (more
+# than 1024 lines) the ring (r <= 15), registers (16..64) and the stream.
+SWEEPS = [
+    (760, [1, 15, 16, 17, 31, 32, 33, 46, 47, 48, 49, 50, 63, 64, 65, 79, 80, 81, 95, 96, 97, 127, 128, 129,
+           175, 176, 177, 190, 191, 192, 193, 194, 255, 300, 379, 380, 759]),
+    (1100, [14, 15, 16, 17, 31, 32, 33, 47, 48, 49, 63, 64, 65, 66, 200]),
+]
+
+
+@pytest.mark.parametrize("side,radii", SWEEPS)
+def test_blur_radius_sweep_large_grid(env, side, radii):
+    torch, plas, ctx, ref = env
+    d = 59
+    rng = np.random.default_rng(side)
+    G = (rng.standard_normal((side * side, d)) * rng.uniform(0.01, 10, d)).astype(np.float32)
+    dp = plas.padded_channels(d)
+    g = to_working_layout(torch, G, dp)
+    for r in radii:
+        T = from_working_layout(ctx.stage_blur(g, side, r), d)
+        want = ref.blur(G, side, r)
+        assert np.array_equal(bits(T), bits(want)), (side, r)
+
+
 def test_blur_padding_stays_zero(env):
     torch, plas, ctx, ref = env
     G = np.random.default_rng(1).standard_normal((20 * 20, 5)).astype(np.float32)
